@@ -1,0 +1,177 @@
+"""Throughput benchmark of the ensemble integrator on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--config NAME] [--no-cpu-baseline]
+
+A step is one full solve of a parameter sweep (every system integrated over
+its whole horizon, all events, accessories and records), starting from the
+same seeded inputs already resident in HBM.  Prints ONE JSON line with
+accepted system-steps/s over the timed steps, the FP64 roofline position of
+the integrator kernel (timed with HIP events on the stream it runs on) and
+the CPU oracle timed on a bounded sample of the same sweep.
+
+Default workload: Duffing x'' + k x' + x + x^3 = B cos t, Cash-Karp at
+rtol = atol = 1e-10, 2^17 systems on a (k, B) grid, 1088 forcing periods,
+local maxima of x located by events and recorded over the last 64.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "system-steps/s + % FP64 VALU peak (RKCK45 sweep); p50/p99 sweep latency"
+FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
+
+# Algorithmic FP64 operations per attempted step (FMA = 2, add/mul/div/sqrt = 1)
+# counted from the method and the model's right-hand side, plus the number of
+# transcendental calls per attempt (cos, sin/cos pairs, pow); the FLOP value
+# of one call is TRANS_FLOPS (a minimax polynomial of the libm kind).
+ARITH_PER_ATTEMPT = {
+    ("duffing", "rkck45"): 131 + 6 * 10,
+    ("duffing", "rk4"): 30 + 4 * 10,
+    ("keller_miksis", "rkck45"): 131 + 6 * 38,
+    ("relief_valve", "rkck45"): 183 + 6 * 9,
+}
+TRANS_PER_ATTEMPT = {
+    ("duffing", "rkck45"): 6 + 1,
+    ("duffing", "rk4"): 4,
+    ("keller_miksis", "rkck45"): 6 * 3 + 1,
+    ("relief_valve", "rkck45"): 1,
+}
+TRANS_FLOPS = 40
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="duffing_rkck45",
+                    choices=["duffing_rk4", "duffing_rkck45", "keller_miksis", "relief_valve"])
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(pb, target_s):
+    """The oracle, as it is, on a stratified sample of the same sweep over the
+    full horizon, on all host cores; accepted system-steps/s."""
+    from oracle import oracle as O
+    from paper_1810_03931_amd import inputs as I
+    cores = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    pilot = pb.subset(I.stratified_sample(pb.n, 2 * threads, seed=21))
+    t0 = time.perf_counter()
+    O.solve(pilot.model, pilot.method, pilot.time_domain.copy(), pilot.state.copy(),
+            pilot.params, threads=threads, **pilot.options)
+    per_sys = (time.perf_counter() - t0) / pilot.n
+    k = int(min(pb.n, max(2 * threads, target_s / max(per_sys, 1e-9))))
+    sample = pb.subset(I.stratified_sample(pb.n, k, seed=22))
+    t0 = time.perf_counter()
+    r = O.solve(sample.model, sample.method, sample.time_domain.copy(), sample.state.copy(),
+                sample.params, threads=threads, **sample.options)
+    dt = time.perf_counter() - t0
+    acc = int(r["counts"][0].sum())
+    return {"value": acc / dt, "unit": "system-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} of {pb.n} systems (stratified), full horizon, {acc} accepted steps "
+                      f"in {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the systems are independent and this build "
+              "measures the single-GPU kernel (see the design notes for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1810_03931_amd import ensemble as E
+    from paper_1810_03931_amd import inputs as I
+
+    if not os.path.exists(E.LIB_PATH):
+        from paper_1810_03931_amd import build
+        build.build()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pb = I.CONFIGS[args.config]()
+    ens = E.Ensemble(pb.model, pb.method, block_size=args.block_size)
+    td0 = torch.as_tensor(pb.time_domain, device=dev).contiguous()
+    y0 = torch.as_tensor(pb.state, device=dev).contiguous()
+    p = torch.as_tensor(pb.params, device=dev).contiguous()
+    td, y = td0.clone(), y0.clone()
+    ev = pb.options.get("events", [])
+    cap = pb.options.get("record_cap", 0) if any(e.get("record_component", -1) >= 0 for e in ev) else 0
+    out = ens.outputs(pb.n, n_accessories=len(pb.options.get("accessories", [])),
+                      n_events=len(ev), record_cap=cap, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        td.copy_(td0)
+        y.copy_(y0)
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        ens.solve(td, y, p, out=out, stream=stream, **pb.options)
+        k1.record(stream)
+        return k0, k1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    kernel_events, wall = [], []
+    s0.record(stream)
+    for _ in range(args.steps):
+        w0 = time.perf_counter()
+        kernel_events.append(step())
+        torch.cuda.synchronize()
+        wall.append(time.perf_counter() - w0)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = s0.elapsed_time(s1)
+    kernel_ms = np.array([a.elapsed_time(b) for a, b in kernel_events])
+
+    counts = out["counts"].sum(dim=1).cpu().numpy()        # accepted, rejected, location
+    status = np.bincount(out["status"].cpu().numpy() & 0xFF, minlength=6)
+    accepted, attempts = int(counts[0]), int(counts.sum())
+    ms_per_step = total_ms / args.steps
+    value = accepted / (ms_per_step / 1e3)
+
+    key = (pb.model, pb.method)
+    flops_attempt = ARITH_PER_ATTEMPT[key] + TRANS_PER_ATTEMPT[key] * TRANS_FLOPS
+    kern_s = float(kernel_ms.mean()) / 1e3
+    achieved = attempts * flops_attempt / kern_s / 1e12
+    info = ens.info()
+    line = {
+        "metric": METRIC, "value": value, "unit": "system-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded parameter sweep)",
+        "config": {"workload": pb.name, "systems": pb.n, "model": pb.model, "method": pb.method,
+                   "horizon": float(pb.time_domain[1, 0]), "t_record": pb.options.get("t_record"),
+                   "rtol": pb.options.get("rtol"), "block_size": info["block_size"],
+                   "resident_systems": info["resident_systems"]},
+        "attempted_steps_per_s": attempts / (ms_per_step / 1e3),
+        "reject_frac": float(counts[1] / attempts), "location_frac": float(counts[2] / attempts),
+        "status_counts": status.tolist(),
+        "p50_ms": float(np.percentile(np.array(wall) * 1e3, 50)),
+        "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
+        "kernel_ms": float(kernel_ms.mean()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_attempt": flops_attempt, "attempts_per_launch": attempts},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * ode_ensemble.h -- C ABI of the MI355X (gfx950) ensemble ODE integrator.
+ *
+ * Integrates very many small, independent ODE systems y' = f(y, t; p), one
+ * system per GPU lane, with the adaptive Runge-Kutta-Cash-Karp 4(5) scheme or
+ * fixed-step classical RK4 (paper: Hegedus, arXiv:1810.03931, Sec. 3).
+ * Trajectories are never stored; per-system "accessories" (running extrema
+ * and their times, Sec. 5), event detection with secant location, event
+ * actions such as impact laws, and stop conditions (Sec. 4, Sec. 6.6) are
+ * evaluated on the fly.
+ *
+ * Layout (paper Sec. 6.1, problem pool): every per-system array is a
+ * structure of arrays with leading dimension `ld`; component i of system s
+ * is at index i*ld + s.  All array arguments are DEVICE pointers owned by
+ * the caller, who keeps them alive until the stream passed to
+ * ode_ensemble_solve has completed.  The library never copies them to the
+ * host.
+ *
+ * Errors: every call returns ODE_OK (0) or a negative ode_error code, and
+ * then ode_ensemble_last_error() describes the problem (thread-local string).
+ * Numerical outcomes of individual systems (NaN at the minimum step, event
+ * stop, equilibrium stop, step budget) are NOT call errors: they are written
+ * to the per-system status array.
+ */
+#ifndef ODE_ENSEMBLE_H
+#define ODE_ENSEMBLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ODE_MAX_STATE 8
+#define ODE_MAX_EVENTS 4
+#define ODE_MAX_ACCESSORIES 4
+#define ODE_MAX_STEPS_LIMIT 2000000000LL /* largest accepted max_steps */
+
+/* Call results. */
+enum ode_error {
+  ODE_OK = 0,
+  ODE_EINVAL = -1,  /* an argument is invalid (checked before any GPU work) */
+  ODE_ENOMEM = -2,  /* a device or host allocation failed                  */
+  ODE_EHIP = -3,    /* a HIP runtime call failed                            */
+  ODE_ENOTSUP = -4  /* valid request this build does not implement         */
+};
+
+/* Built-in models (paper Sec. 2).  Parameters, in order:
+ *   DUFFING        2 states, 5 params (k, B, omega, lin, cub):
+ *                  y1' = y2, y2' = -lin*y1 - cub*y1^3 - k*y2 + B*cos(omega*t)
+ *                  (Sec. 2.1; the paper's double well is lin = -1, cub = 1).
+ *   KELLER_MIKSIS  2 states, 13 params C0..C12 of the dimensionless form of
+ *                  Sec. 2.2 (time is tau, one period of the first forcing).
+ *   RELIEF_VALVE   3 states, 5 params (kappa, delta, beta, q, r), Sec. 2.3;
+ *                  r is available to event actions through action_param.
+ *   BALLISTIC      2 states, 1 param (g): y1' = y2, y2' = -g (test model). */
+enum ode_model {
+  ODE_MODEL_DUFFING = 1,
+  ODE_MODEL_KELLER_MIKSIS = 2,
+  ODE_MODEL_RELIEF_VALVE = 3,
+  ODE_MODEL_BALLISTIC = 4
+};
+
+/* Integration schemes (paper Sec. 3 and Sec. 6.4). */
+enum ode_method { ODE_RKCK45 = 0, ODE_RK4 = 1 };
+
+/* Arithmetic of the integrator.  FP64 is the paper's (Sec. 6.1). */
+enum ode_precision { ODE_FP64 = 0 };
+
+/* Accessory kinds (paper Sec. 5 and Sec. 6.7): a running maximum or minimum
+ * of one state component over the recording window, with the time at which
+ * it was first reached.  Accessory a occupies rows 2a (value) and 2a+1
+ * (time) of the accessories array. */
+enum ode_accessory_kind { ODE_ACC_MAX = 1, ODE_ACC_MIN = 2 };
+
+/* Per-system status (low byte) and flags. */
+enum ode_lane_status {
+  ODE_LANE_DONE = 0,             /* reached t1                                  */
+  ODE_LANE_STOP_EVENT = 1,       /* an event reached its stop count (Sec. 6.6)  */
+  ODE_LANE_STOP_EQUILIBRIUM = 2, /* max_equilibrium_steps accepted steps inside
+                                    an event zone (Sec. 4, configuration d)    */
+  ODE_LANE_FAIL_NAN = 3,         /* NaN with the minimum step (Sec. 6.5)        */
+  ODE_LANE_MAX_STEPS = 4,        /* max_steps attempts used                     */
+  ODE_LANE_BAD_INPUT = 5         /* non-finite t0 or t1                         */
+};
+#define ODE_LANE_FLAG_SECANT_CAP 0x100 /* an event location hit its 50-iteration cap */
+
+/* Event j: F_j = y[component] - level (paper Sec. 4: F_Ej(y, t) = 0 with a
+ * zone of half width `tolerance` around it; Sec. 6.6 event properties). */
+typedef struct {
+  int32_t component;        /* state component the event watches            */
+  int32_t direction;        /* -1: F decreasing, +1: F increasing, 0: both   */
+  int32_t stop_after;       /* stop the system at this detection; 0: never   */
+  int32_t action_component; /* -1: no action; else y[c] <- coef * y[c]       */
+  int32_t action_param;     /* -1: coef = action_coef; else action_coef*p[i] */
+  int32_t record_component; /* -1: none; else store (t, y[c]) of every event
+                               inside the window (at most one event records) */
+  double level;
+  double tolerance;         /* >= 0                                          */
+  double action_coef;
+} ode_event_spec;
+
+typedef struct {
+  int32_t kind;      /* ode_accessory_kind */
+  int32_t component;
+} ode_accessory_spec;
+
+/* What a handle integrates: the kernel is chosen here (paper Sec. 6.2,
+ * solver object; Sec. 6.4, solver choice). */
+typedef struct {
+  int32_t model;      /* ode_model                                          */
+  int32_t method;     /* ode_method                                         */
+  int32_t precision;  /* ode_precision                                      */
+  int32_t block_size; /* threads per workgroup, multiple of 64 in [64, 256];
+                         0 selects the library default                      */
+} ode_ensemble_desc;
+
+/* One integration call (paper Sec. 6.4 Solve; Sec. 6.5 ODE properties;
+ * Sec. 6.6 event properties; Sec. 6.7 accessories; Sec. 6.8 finalization).
+ * All pointers are device pointers; rows are indexed by r*ld + s. */
+typedef struct {
+  int64_t n_systems;          /* systems to integrate; with system_index this
+                                 is its length                              */
+  int64_t ld;                 /* leading dimension: ld >= n_systems without
+                                 system_index, ld >= 1 with it              */
+  double *time_domain;        /* [2][ld] in: (t0, t1); out: row 0 <- final t */
+  double *state;              /* [n_state][ld] in: y0; out: final y          */
+  const double *params;       /* [n_param][ld], never written                */
+  double *accessories;        /* [2*n_accessories][ld] out; NULL iff none    */
+  double *next_h;             /* [ld] in: step to start with if > 0 (RKCK45);
+                                 out: step to continue with; may be NULL     */
+  int32_t *status;            /* [ld] out: ode_lane_status | flags           */
+  int64_t *counts;            /* [3][ld] out: accepted, rejected and event-
+                                 location attempts; may be NULL             */
+  int32_t *event_counts;      /* [n_events][ld] out: detections inside the
+                                 recording window; may be NULL              */
+  double *event_records;      /* [event_record_capacity][2][ld] out: (t, y[c])
+                                 of recorded events in order; detections past
+                                 the capacity are counted, not stored; NULL
+                                 iff capacity is 0                           */
+  const int64_t *system_index;/* [n_systems] systems to integrate (paper
+                                 Sec. 6.3 RandomSet); NULL: 0..n_systems-1.
+                                 Entries outside [0, ld) are skipped        */
+  double rtol[ODE_MAX_STATE]; /* per component, >= 0, rtol+atol > 0 (RKCK45) */
+  double atol[ODE_MAX_STATE];
+  double h0;                  /* initial step (RKCK45) or fixed step (RK4), > 0 */
+  double h_min;               /* RKCK45: > 0; at h_min steps are accepted
+                                 whatever the error (Sec. 6.5)               */
+  double h_max;               /* RKCK45: >= h_min                            */
+  double grow;                /* RKCK45: largest step growth, >= 1           */
+  double shrink;              /* RKCK45: smallest step factor, in (0, 1]     */
+  double t_record;            /* start of the recording window (absolute
+                                 time); accessories are initialised from the
+                                 state there (Sec. 6.8) and event counts and
+                                 records only cover t >= t_record            */
+  int64_t max_steps;          /* attempt budget per system, 1..ODE_MAX_STEPS_LIMIT */
+  int32_t max_equilibrium_steps; /* >= 0; 0 disables the equilibrium stop   */
+  int32_t n_events;           /* 0..ODE_MAX_EVENTS                           */
+  int32_t n_accessories;      /* 0..ODE_MAX_ACCESSORIES                      */
+  int32_t event_record_capacity; /* >= 0                                     */
+  ode_event_spec events[ODE_MAX_EVENTS];
+  ode_accessory_spec accessory_specs[ODE_MAX_ACCESSORIES];
+} ode_solve_args;
+
+/* Opaque handle: one solver object per (model, method, precision) and device
+ * (paper Sec. 6.2).  It owns only its small device work-queue counters. */
+typedef struct ode_ensemble ode_ensemble;
+
+/* Launch facts of a handle (for measurement and tuning). */
+typedef struct {
+  int32_t block_size;         /* threads per workgroup                      */
+  int32_t blocks_per_cu;      /* resident workgroups per compute unit       */
+  int32_t compute_units;      /* of the handle's device                     */
+  int32_t max_grid;           /* workgroups of a full persistent launch     */
+  int64_t resident_systems;   /* systems integrated concurrently at most    */
+} ode_ensemble_info;
+
+/* Number of states and parameters of a built-in model.  Host only, needs no
+ * GPU.  Returns ODE_OK or ODE_EINVAL for an unknown model. */
+int ode_ensemble_model_dims(int32_t model, int32_t *n_state, int32_t *n_param);
+
+/* Create a handle for one (model, method, precision) on the current HIP
+ * device (paper Sec. 6.2: a solver object per device, created after the
+ * device is selected).  Allocates the handle's small device work-queue
+ * counters.  *out is set to NULL on failure.  Errors: ODE_EINVAL (NULL
+ * arguments, unknown model/method/precision, bad block size), ODE_ENOMEM,
+ * ODE_EHIP. */
+int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out);
+
+/* Enqueue one integration of args->n_systems systems on `hip_stream` (a
+ * hipStream_t; NULL is the default stream) and return without waiting.
+ * Every system is integrated from its own t0 to t1 (paper Sec. 6.1, each
+ * system has its own time domain) and its results are written in place:
+ * final state, final time into t0 (so a second call continues, Sec. 6.8),
+ * next step, status, counts, accessories, event counts and records.
+ * Arguments are validated before anything is enqueued (ODE_EINVAL); a HIP
+ * launch failure returns ODE_EHIP.  One handle must not run two solves at
+ * the same time; separate handles may run concurrently. */
+int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *args, void *hip_stream);
+
+/* Launch facts for the handle.  Errors: ODE_EINVAL for NULL arguments. */
+int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info);
+
+/* Release the handle and its device memory.  NULL is ignored.  The caller
+ * must have synchronised every stream the handle was used on. */
+void ode_ensemble_destroy(ode_ensemble *e);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *ode_ensemble_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ODE_ENSEMBLE_H */

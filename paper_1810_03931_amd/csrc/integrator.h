@@ -1,0 +1,78 @@
+// Internal interface between the C ABI (api.cpp) and the integrator kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace odeens {
+
+constexpr int kMaxState = 8;
+constexpr int kMaxEvents = 4;
+constexpr int kMaxAcc = 4;
+constexpr int kMaxBlock = 256;
+constexpr int kSecantMaxIter = 50;
+
+enum LaneStatus : int32_t {
+  kDone = 0,
+  kStopEvent = 1,
+  kStopEquilibrium = 2,
+  kFailNan = 3,
+  kMaxSteps = 4,
+  kBadInput = 5,
+  kRunning = -1
+};
+constexpr int32_t kFlagSecantCap = 0x100;
+
+struct EventCtl {
+  int32_t component, direction, stop_after, action_component, action_param, record_component;
+  double level, tolerance, action_coef;
+};
+
+struct AccCtl {
+  int32_t kind, component;  // kind: 1 max, 2 min
+};
+
+// Solver-wide constants.  Passed by value: they live in the kernel-argument
+// segment and every wave reads them into scalar registers, so the per-lane
+// vector registers stay free for the integration state.
+struct Control {
+  double rtol[kMaxState], atol[kMaxState];
+  double h0, h_min, h_max, grow, shrink, t_record;
+  int32_t max_steps;
+  int32_t max_eq;
+  int32_t n_events, n_acc, rec_cap, pad;
+  EventCtl ev[kMaxEvents];
+  AccCtl acc[kMaxAcc];
+};
+
+// Per-system arrays (structure of arrays, row r of system s at r*ld + s)
+// and the persistent work queue.
+struct Arrays {
+  double *td;
+  double *y;
+  const double *p;
+  double *acc;
+  double *next_h;
+  int32_t *status;
+  int64_t *counts;
+  int32_t *evc;
+  double *rec;
+  const int64_t *index;
+  int64_t n, ld;
+  unsigned long long *queue;  // [0] next queue position, [1] finished waves
+  uint32_t total_waves;
+};
+
+// Compile-time variants: number of event / accessory slots compiled in.
+inline int event_slots(int n_events) { return n_events == 0 ? 0 : (n_events == 1 ? 1 : 4); }
+inline int acc_slots(int n_acc) { return n_acc == 0 ? 0 : (n_acc <= 2 ? 2 : 4); }
+
+// The kernel for (model, method, event slots, accessory slots), or nullptr.
+const void *integrator_kernel(int model, int method, int nev, int nacc);
+
+// Launch it with `grid` workgroups of `block` threads on `stream`.
+hipError_t launch_integrator(int model, int method, int nev, int nacc, const Control &c,
+                             const Arrays &a, int grid, int block, hipStream_t stream);
+
+}  // namespace odeens

@@ -1,0 +1,582 @@
+// Persistent ensemble integrator kernel (paper: Hegedus, arXiv:1810.03931).
+//
+// One lane integrates one system at a time with its state in registers.  A
+// wave pulls system indices from a device-wide queue: whenever some of its
+// lanes are idle it claims that many indices with one atomic (ballot +
+// popcount), hands them out by lane rank (mbcnt), and the wave leaves only
+// when the queue is empty and all its lanes are idle.  Systems that finish
+// early -- short horizons, event or equilibrium stops, NaN stops -- are thus
+// replaced at once instead of idling until the slowest lane of the wave is
+// done (the paper attributes its lower utilisation to exactly this
+// divergence, Sec. 7.1.1 and Sec. 7.2-7.3).
+//
+// Every loop iteration performs exactly one Runge-Kutta attempt per busy
+// lane: a normal step, a step the error test rejects, or one secant iterate
+// of an event location.  Lanes in different phases therefore still execute
+// the expensive stage evaluations together; only the cheap bookkeeping after
+// the attempt diverges.
+#pragma once
+
+#include "integrator.h"
+#include "models.h"
+
+namespace odeens {
+
+// Cash-Karp 4(5) coefficients (Cash & Karp 1990; the paper names the
+// method in Sec. 3 without printing them).  e = b - b* are the error weights.
+namespace ck {
+constexpr double c2 = 1.0 / 5.0, c3 = 3.0 / 10.0, c4 = 3.0 / 5.0, c6 = 7.0 / 8.0;
+constexpr double a21 = 1.0 / 5.0;
+constexpr double a31 = 3.0 / 40.0, a32 = 9.0 / 40.0;
+constexpr double a41 = 3.0 / 10.0, a42 = -9.0 / 10.0, a43 = 6.0 / 5.0;
+constexpr double a51 = -11.0 / 54.0, a52 = 5.0 / 2.0, a53 = -70.0 / 27.0, a54 = 35.0 / 27.0;
+constexpr double a61 = 1631.0 / 55296.0, a62 = 175.0 / 512.0, a63 = 575.0 / 13824.0,
+                 a64 = 44275.0 / 110592.0, a65 = 253.0 / 4096.0;
+constexpr double b1 = 37.0 / 378.0, b3 = 250.0 / 621.0, b4 = 125.0 / 594.0, b6 = 512.0 / 1771.0;
+constexpr double e1 = -277.0 / 64512.0, e3 = 6925.0 / 370944.0, e4 = -6925.0 / 202752.0,
+                 e5 = -277.0 / 14336.0, e6 = 277.0 / 7084.0;
+}  // namespace ck
+
+enum { kMethodRKCK45 = 0, kMethodRK4 = 1 };
+
+// y[c] for a component index c known only at run time, as a bitmask blend of
+// all components.  (A chain of selects between array elements is folded by
+// the compiler into one dynamically indexed load, which forces the whole array
+// out of registers into scratch memory; masks do not fold that way.)
+template <int N>
+__device__ __forceinline__ double pick(const double (&y)[N], int c) {
+  unsigned long long r = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const unsigned long long m = 0ull - (unsigned long long)(c == i);
+    r |= (unsigned long long)__double_as_longlong(y[i]) & m;
+  }
+  return __longlong_as_double((long long)r);
+}
+
+// y[c] <- v for a run-time component index c (bitmask blend, as in pick).
+template <int N>
+__device__ __forceinline__ void put(double (&y)[N], int c, double v) {
+  const unsigned long long vb = (unsigned long long)__double_as_longlong(v);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const unsigned long long m = 0ull - (unsigned long long)(c == i);
+    const unsigned long long yb = (unsigned long long)__double_as_longlong(y[i]);
+    y[i] = __longlong_as_double((long long)((vb & m) | (yb & ~m)));
+  }
+}
+
+// Stage time t + c*h rounded exactly as written (product, then sum), so that
+// time arguments of the forcing terms carry no contraction-dependent ulp.
+__device__ __forceinline__ double stage_time(double t, double c, double h) {
+  return __dadd_rn(t, __dmul_rn(c, h));
+}
+
+// One Cash-Karp step of length h from (t, y): propagated fifth-order
+// solution y5 and error estimate err = h * sum e_i k_i.
+template <class M>
+__device__ __forceinline__ void cash_karp_attempt(double t, const double (&y)[M::NS],
+                                                  const double (&p)[M::NP], double h,
+                                                  double (&y5)[M::NS], double (&err)[M::NS]) {
+  constexpr int N = M::NS;
+  double k1[N], k2[N], k3[N], k4[N], k5[N], k6[N], ys[N];
+  M::rhs(t, y, p, k1);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, ck::a21 * k1[i], y[i]);
+  M::rhs(stage_time(t, ck::c2, h), ys, p, k2);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, fma(ck::a32, k2[i], ck::a31 * k1[i]), y[i]);
+  M::rhs(stage_time(t, ck::c3, h), ys, p, k3);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = fma(h, fma(ck::a43, k3[i], fma(ck::a42, k2[i], ck::a41 * k1[i])), y[i]);
+  M::rhs(stage_time(t, ck::c4, h), ys, p, k4);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = fma(h, fma(ck::a54, k4[i], fma(ck::a53, k3[i], fma(ck::a52, k2[i], ck::a51 * k1[i]))),
+                y[i]);
+  M::rhs(t + h, ys, p, k5);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = fma(h,
+                fma(ck::a65, k5[i],
+                    fma(ck::a64, k4[i], fma(ck::a63, k3[i], fma(ck::a62, k2[i], ck::a61 * k1[i])))),
+                y[i]);
+  M::rhs(stage_time(t, ck::c6, h), ys, p, k6);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    y5[i] = fma(h, fma(ck::b6, k6[i], fma(ck::b4, k4[i], fma(ck::b3, k3[i], ck::b1 * k1[i]))), y[i]);
+    err[i] = h * fma(ck::e6, k6[i],
+                     fma(ck::e5, k5[i], fma(ck::e4, k4[i], fma(ck::e3, k3[i], ck::e1 * k1[i]))));
+  }
+}
+
+// One classical RK4 step of length h from (t, y).
+template <class M>
+__device__ __forceinline__ void rk4_attempt(double t, const double (&y)[M::NS],
+                                            const double (&p)[M::NP], double h,
+                                            double (&yn)[M::NS]) {
+  constexpr int N = M::NS;
+  double k1[N], k2[N], k3[N], k4[N], ys[N];
+  const double hh = 0.5 * h;
+  M::rhs(t, y, p, k1);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = fma(hh, k1[i], y[i]);
+  M::rhs(t + hh, ys, p, k2);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = fma(hh, k2[i], y[i]);
+  M::rhs(t + hh, ys, p, k3);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, k3[i], y[i]);
+  M::rhs(t + h, ys, p, k4);
+  const double h6 = h * (1.0 / 6.0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) yn[i] = fma(h6, fma(2.0, k2[i] + k3[i], k1[i] + k4[i]), y[i]);
+}
+
+// Event detection between the last accepted point (Fo, outside the zone) and
+// the candidate (Fn): 0 none, 1 the step jumped over the zone (needs
+// location), 2 the step ended inside the zone.  Direction -1 is F
+// decreasing, +1 increasing, 0 both (paper Sec. 4 and Sec. 6.6).
+__device__ __forceinline__ int detect(double Fo, double Fn, int dir, double tol) {
+  const bool inside = fabs(Fn) <= tol;
+  int r = 0;
+  if (dir <= 0 && Fo > tol) r = (Fn < -tol) ? 1 : (inside ? 2 : 0);
+  if (r == 0 && dir >= 0 && Fo < -tol) r = (Fn > tol) ? 1 : (inside ? 2 : 0);
+  return r;
+}
+
+// Next step length of the event location: the secant root through the last
+// two iterates, or the midpoint of the bracket (lo, hi) when the secant root
+// leaves it.  Plain roundings, no contraction.
+__device__ __forceinline__ double secant(double sa, double ga, double sb, double gb, double lo,
+                                         double hi) {
+  const double sc = __dsub_rn(sb, __ddiv_rn(__dmul_rn(gb, __dsub_rn(sb, sa)), __dsub_rn(gb, ga)));
+  return (sc > lo && sc < hi) ? sc : __dmul_rn(0.5, __dadd_rn(lo, hi));
+}
+
+template <class M, int METHOD, int NEV, int NACC>
+__global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, const Arrays a) {
+  constexpr int N = M::NS;
+  constexpr int P = M::NP;
+  constexpr int EV = NEV > 0 ? NEV : 1;
+  constexpr int AC = NACC > 0 ? NACC : 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t ld = a.ld;
+
+  // ---- per-lane system state (registers) ----
+  int64_t s = -1;
+  bool active = false;
+  double t = 0.0, t1 = 0.0, h = 0.0;
+  double y[N], p[P];
+  int32_t attempts = 0, n_acc = 0, n_rej = 0, flags = 0, status = kRunning;
+  bool window_open = false;
+  double accv[AC], acct[AC];
+  double seg_start = 0.0;  // RK4: the state after m steps of a segment is at seg_start + m*dt
+  int32_t seg_steps = 0;
+  double F[EV];
+  int32_t zone[EV], cnt[EV], wcnt[EV];
+  uint32_t leaving = 0;    // bit j: inside the zone of event j
+  int32_t n_rec = 0;
+  // secant location of event J over step lengths in (lo, hi)
+  bool locating = false;
+  int32_t loc_it = 0, loc_c = 0;
+  double loc_level = 0.0, loc_tol = 0.0;
+  bool loc_pos = false;    // sign of F_J at the start of the step
+  double lo = 0.0, hi = 0.0, sa = 0.0, ga = 0.0, sb = 0.0, gb = 0.0, sc = 0.0, h_keep = 0.0;
+  uint32_t loc_bit = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) y[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) p[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < EV; ++j) F[j] = 0.0, zone[j] = cnt[j] = wcnt[j] = 0;
+#pragma unroll
+  for (int k = 0; k < AC; ++k) accv[k] = acct[k] = 0.0;
+
+  bool exhausted = false;  // wave-uniform
+
+  auto acc_init = [&]() {
+#pragma unroll
+    for (int k = 0; k < NACC; ++k)
+      if (k < c.n_acc) {
+        accv[k] = pick(y, c.acc[k].component);
+        acct[k] = t;
+      }
+  };
+
+  auto retire = [&]() {
+    if (!window_open) acc_init();  // window never opened: describe the final point
+    a.td[s] = t;
+#pragma unroll
+    for (int i = 0; i < N; ++i) a.y[i * ld + s] = y[i];
+    if (a.next_h) a.next_h[s] = h;
+    a.status[s] = status | flags;
+    if (a.counts) {
+      a.counts[s] = n_acc;
+      a.counts[ld + s] = n_rej;
+      a.counts[2 * ld + s] = attempts - n_acc - n_rej;
+    }
+#pragma unroll
+    for (int k = 0; k < NACC; ++k)
+      if (k < c.n_acc) {
+        a.acc[(2 * k) * ld + s] = accv[k];
+        a.acc[(2 * k + 1) * ld + s] = acct[k];
+      }
+    if (a.evc) {
+#pragma unroll
+      for (int j = 0; j < NEV; ++j)
+        if (j < c.n_events) a.evc[j * ld + s] = wcnt[j];
+    }
+    active = false;
+  };
+
+  for (;;) {
+    // ---- refill idle lanes from the queue (all 64 lanes are converged here) ----
+    const unsigned long long need = __ballot(!active);
+    if (need != 0 && !exhausted) {
+      const uint32_t k = __popcll(need);
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)k);
+      base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+             (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base);
+      if (base + k >= (unsigned long long)a.n) exhausted = true;
+      if (!active) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+        const unsigned long long q = base + rank;
+        if (q < (unsigned long long)a.n) {
+          const int64_t cand = a.index ? a.index[q] : (int64_t)q;
+          if (cand >= 0 && cand < ld) {
+            s = cand;
+            active = true;
+            // ---- load and initialise the system ----
+            t = a.td[s];
+            t1 = a.td[ld + s];
+#pragma unroll
+            for (int i = 0; i < N; ++i) y[i] = a.y[i * ld + s];
+#pragma unroll
+            for (int j = 0; j < P; ++j) p[j] = a.p[j * ld + s];
+            attempts = n_acc = n_rej = flags = 0;
+            status = kRunning;
+            locating = false;
+            seg_start = t;
+            seg_steps = 0;
+            n_rec = 0;
+            leaving = 0;
+            if (METHOD == kMethodRK4) {
+              h = c.h0;
+            } else {
+              h = c.h0;
+              if (a.next_h) {
+                const double hn = a.next_h[s];
+                if (hn > 0.0 && isfinite(hn)) h = hn;
+              }
+              h = fmin(fmax(h, c.h_min), c.h_max);
+            }
+#pragma unroll
+            for (int j = 0; j < NEV; ++j) {
+              zone[j] = cnt[j] = wcnt[j] = 0;
+              if (j < c.n_events) {
+                F[j] = pick(y, c.ev[j].component) - c.ev[j].level;
+                // an initial point inside a zone is not an event (paper Sec. 7.2)
+                if (fabs(F[j]) <= c.ev[j].tolerance) leaving |= 1u << j;
+              }
+            }
+            window_open = false;
+            if (!isfinite(t) || !isfinite(t1)) {
+              status = kBadInput;
+            } else if (c.t_record <= t) {
+              window_open = true;
+              acc_init();
+            }
+            if (status == kRunning && t >= t1) status = kDone;
+            if (status != kRunning) retire();
+          }
+        }
+      }
+    }
+    if (__ballot(active) == 0) {
+      if (exhausted) break;
+      continue;
+    }
+    if (!active) continue;
+
+    // ---- choose this attempt's step length ----
+    double t_b = t1, h_att;
+    bool clipped = false;
+    if (locating) {
+      h_att = sc;
+    } else {
+      t_b = (!window_open && c.t_record < t1) ? c.t_record : t1;
+      if (METHOD == kMethodRK4) {
+        const double t_grid = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), c.h0));
+        if (t_grid >= __dsub_rn(t_b, __dmul_rn(1e-9, c.h0))) {
+          h_att = t_b - t;
+          clipped = true;
+        } else {
+          h_att = c.h0;
+        }
+      } else {
+        h_att = h;
+        if (h_att >= t_b - t) {
+          h_att = t_b - t;
+          clipped = true;
+        }
+      }
+    }
+
+    // ---- the attempt: one full method step from (t, y) ----
+    double yn[N], err[N];
+    if (METHOD == kMethodRK4)
+      rk4_attempt<M>(t, y, p, h_att, yn);
+    else
+      cash_karp_attempt<M>(t, y, p, h_att, yn, err);
+    ++attempts;
+
+    bool commit = false, located = false;
+    double tn = t;
+    uint32_t det = 0;  // events detected by the committed step
+
+    if (!locating) {
+      double h_next = h;
+      bool passed = true;
+      if (METHOD == kMethodRKCK45) {
+        // Error test (paper Sec. 6.5): scaled max norm, step factor
+        // 0.9*E^(-1/5) limited to [shrink, grow]; at h_min every step is
+        // accepted; NaN rejects and shrinks, and stops at h_min.
+        bool has_nan = false;
+        double E = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          has_nan |= isnan(yn[i]);
+          const double sc_i = fma(c.rtol[i], fmax(fabs(y[i]), fabs(yn[i])), c.atol[i]);
+          const double r = fabs(err[i]) / sc_i;
+          has_nan |= isnan(r);
+          E = (r > E) ? r : E;
+        }
+        if (has_nan) {
+          passed = false;
+          if (h_att <= c.h_min) {
+            status = kFailNan;
+          } else {
+            h = fmax(c.h_min, c.shrink * h_att);
+            ++n_rej;
+          }
+        } else {
+          double fac = (E == 0.0) ? c.grow : 0.9 * pow(E, -0.2);
+          fac = fmax(c.shrink, fmin(c.grow, fac));
+          h_next = fmax(c.h_min, fmin(c.h_max, fac * h_att));
+          if (!(E <= 1.0) && h_att > c.h_min) {
+            passed = false;
+            h = h_next;
+            ++n_rej;
+          }
+        }
+      }
+      if (passed) {
+        uint32_t cross = 0, land = 0;
+#pragma unroll
+        for (int j = 0; j < NEV; ++j) {
+          if (j < c.n_events && !((leaving >> j) & 1u)) {
+            const double Fn = pick(yn, c.ev[j].component) - c.ev[j].level;
+            const int d = detect(F[j], Fn, c.ev[j].direction, c.ev[j].tolerance);
+            cross |= (d == 1 ? 1u : 0u) << j;
+            land |= (d == 2 ? 1u : 0u) << j;
+          }
+        }
+        const uint32_t any = cross | land;
+        // the event specified last is the one located precisely (paper Sec. 4)
+        const uint32_t top = any ? (1u << (31 - __clz(any))) : 0u;
+        if (top & cross) {
+          locating = true;
+          loc_bit = top;
+          loc_it = 0;
+#pragma unroll
+          for (int j = 0; j < NEV; ++j)
+            if (top == (1u << j)) {
+              loc_c = c.ev[j].component;
+              loc_level = c.ev[j].level;
+              loc_tol = c.ev[j].tolerance;
+              ga = F[j];
+            }
+          gb = pick(yn, loc_c) - loc_level;
+          loc_pos = ga > 0.0;
+          lo = 0.0;
+          hi = h_att;
+          sa = 0.0;
+          sb = h_att;
+          h_keep = h_next;
+          sc = secant(sa, ga, sb, gb, lo, hi);
+        } else {
+          commit = true;
+          det = any;
+          if (clipped)
+            tn = t_b;
+          else if (METHOD == kMethodRK4)
+            tn = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), c.h0));
+          else
+            tn = t + h_att;
+          if (METHOD == kMethodRKCK45) {
+            // after a step clipped to a boundary, do not shrink below the
+            // step in use before the clip
+            h = (clipped && h_next < h) ? h : h_next;
+          }
+        }
+      }
+    } else {
+      // one secant iterate of the location of event J
+      const double gc = pick(yn, loc_c) - loc_level;
+      ++loc_it;
+      const bool found = fabs(gc) <= loc_tol;
+      if (found || loc_it >= kSecantMaxIter) {
+        if (!found) flags |= kFlagSecantCap;
+        commit = true;
+        located = true;
+        locating = false;
+        tn = t + sc;
+        h = h_keep;  // the proposal from the full step stands
+        det = loc_bit;
+#pragma unroll
+        for (int j = 0; j < NEV; ++j) {
+          if (j < c.n_events && (1u << j) != loc_bit && !((leaving >> j) & 1u)) {
+            const double Fn = pick(yn, c.ev[j].component) - c.ev[j].level;
+            det |= (detect(F[j], Fn, c.ev[j].direction, c.ev[j].tolerance) != 0 ? 1u : 0u) << j;
+          }
+        }
+      } else {
+        if ((gc > 0.0) == loc_pos)
+          lo = sc;
+        else
+          hi = sc;
+        sa = sb;
+        ga = gb;
+        sb = sc;
+        gb = gc;
+        sc = secant(sa, ga, sb, gb, lo, hi);
+      }
+    }
+
+    if (commit) {
+      t = tn;
+#pragma unroll
+      for (int i = 0; i < N; ++i) y[i] = yn[i];
+      ++n_acc;
+      if (METHOD == kMethodRK4) {
+        if (located || clipped) {
+          seg_start = t;
+          seg_steps = 0;
+        } else {
+          ++seg_steps;
+        }
+      }
+      // ordinary accessories (paper Sec. 6.7) inside the recording window,
+      // initialised when it opens (Sec. 6.8)
+      if (!window_open) {
+        if (t >= c.t_record) {
+          window_open = true;
+          acc_init();
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k)
+          if (k < c.n_acc) {
+            const double v = pick(y, c.acc[k].component);
+            const bool better = (c.acc[k].kind == 1) ? (v > accv[k]) : (v < accv[k]);
+            accv[k] = better ? v : accv[k];
+            acct[k] = better ? t : acct[k];
+          }
+      }
+      // event hooks in increasing index: counter, window count and record,
+      // action (e.g. the impact law), stop count (paper Sec. 6.6)
+#pragma unroll
+      for (int j = 0; j < NEV; ++j) {
+        if ((det >> j) & 1u) {
+          ++cnt[j];
+          if (window_open) {
+            ++wcnt[j];
+            if (c.ev[j].record_component >= 0) {
+              if (n_rec < c.rec_cap) {
+                a.rec[(int64_t)(2 * n_rec) * ld + s] = t;
+                a.rec[(int64_t)(2 * n_rec + 1) * ld + s] = pick(y, c.ev[j].record_component);
+              }
+              ++n_rec;
+            }
+          }
+          if (c.ev[j].action_component >= 0) {
+            double coef = c.ev[j].action_coef;
+            if (c.ev[j].action_param >= 0) coef *= pick(p, c.ev[j].action_param);
+            put(y, c.ev[j].action_component, coef * pick(y, c.ev[j].action_component));
+          }
+          if (c.ev[j].stop_after > 0 && cnt[j] == c.ev[j].stop_after) status = kStopEvent;
+        }
+      }
+      // zone states: normal exactly when outside the zone; accepted steps
+      // that stay inside after a detection count towards the equilibrium stop
+#pragma unroll
+      for (int j = 0; j < NEV; ++j) {
+        if (j < c.n_events) {
+          F[j] = pick(y, c.ev[j].component) - c.ev[j].level;
+          const bool inside = fabs(F[j]) <= c.ev[j].tolerance;
+          const uint32_t bit = 1u << j;
+          if (((det | ~leaving) & bit) != 0) {
+            leaving = inside ? (leaving | bit) : (leaving & ~bit);
+            zone[j] = 0;
+          } else if (inside) {
+            ++zone[j];
+            if (c.max_eq > 0 && zone[j] >= c.max_eq && status == kRunning)
+              status = kStopEquilibrium;
+          } else {
+            leaving &= ~bit;
+            zone[j] = 0;
+          }
+        }
+      }
+      if (status == kRunning && t >= t1) status = kDone;
+    }
+    if (status == kRunning && !locating && attempts >= c.max_steps) status = kMaxSteps;
+    if (status != kRunning) retire();
+  }
+
+  // The last wave to leave resets the queue for the next launch.
+  if (lane == 0) {
+    __threadfence();
+    const unsigned long long done = atomicAdd(a.queue + 1, 1ull);
+    if (done + 1 == (unsigned long long)a.total_waves) {
+      atomicExch(a.queue, 0ull);
+      atomicExch(a.queue + 1, 0ull);
+    }
+  }
+}
+
+// Instantiation table for one model: kernels for both methods and every
+// compiled (event slots, accessory slots) pair.
+template <class M>
+struct ModelKernels {
+  template <int METHOD, int NEV, int NACC>
+  static const void *fn() {
+    return reinterpret_cast<const void *>(&ode_integrate<M, METHOD, NEV, NACC>);
+  }
+  template <int METHOD>
+  static const void *by_slots(int nev, int nacc) {
+    switch (nev * 10 + nacc) {
+      case 0: return fn<METHOD, 0, 0>();
+      case 2: return fn<METHOD, 0, 2>();
+      case 4: return fn<METHOD, 0, 4>();
+      case 10: return fn<METHOD, 1, 0>();
+      case 12: return fn<METHOD, 1, 2>();
+      case 14: return fn<METHOD, 1, 4>();
+      case 40: return fn<METHOD, 4, 0>();
+      case 42: return fn<METHOD, 4, 2>();
+      case 44: return fn<METHOD, 4, 4>();
+      default: return nullptr;
+    }
+  }
+  static const void *get(int method, int nev, int nacc) {
+    if (method == kMethodRKCK45) return by_slots<kMethodRKCK45>(nev, nacc);
+    if (method == kMethodRK4) return by_slots<kMethodRK4>(nev, nacc);
+    return nullptr;
+  }
+};
+
+}  // namespace odeens

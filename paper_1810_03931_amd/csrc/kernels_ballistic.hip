@@ -1,0 +1,11 @@
+// Integrator kernels specialised for the Ballistic model (one translation unit
+// per model so the instantiations compile in parallel).
+#include "integrator_kernel.h"
+
+namespace odeens {
+
+const void *kernels_ballistic(int method, int nev, int nacc) {
+  return ModelKernels<Ballistic>::get(method, nev, nacc);
+}
+
+}  // namespace odeens

@@ -1,0 +1,11 @@
+// Integrator kernels specialised for the Duffing model (one translation unit
+// per model so the instantiations compile in parallel).
+#include "integrator_kernel.h"
+
+namespace odeens {
+
+const void *kernels_duffing(int method, int nev, int nacc) {
+  return ModelKernels<Duffing>::get(method, nev, nacc);
+}
+
+}  // namespace odeens

@@ -1,0 +1,11 @@
+// Integrator kernels specialised for the ReliefValve model (one translation unit
+// per model so the instantiations compile in parallel).
+#include "integrator_kernel.h"
+
+namespace odeens {
+
+const void *kernels_relief_valve(int method, int nev, int nacc) {
+  return ModelKernels<ReliefValve>::get(method, nev, nacc);
+}
+
+}  // namespace odeens

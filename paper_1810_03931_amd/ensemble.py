@@ -1,0 +1,272 @@
+"""Python binding of the C ABI in ``include/ode_ensemble.h`` (ctypes).
+
+Argument marshalling only: every step of the integration runs in the HIP
+library ``lib/libode_ensemble.so``.  PyTorch supplies device memory and the
+stream.  If the library is missing or cannot be loaded, every call raises --
+there is no CPU fallback.
+
+Arrays are torch float64 (int32/int64 for status, counts and indices) CUDA
+tensors shaped [rows, ld] and C-contiguous; row r of system s is element
+[r, s] (paper Sec. 6.1, problem pool).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Any, Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libode_ensemble.so")
+
+MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4}
+METHOD = {"rkck45": 0, "rk4": 1}
+PRECISION = {"fp64": 0}
+ACC_KIND = {"max": 1, "min": 2}
+MAX_STATE, MAX_EVENTS, MAX_ACC = 8, 4, 4
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSUP = 0, -1, -2, -3, -4
+DONE, STOP_EVENT, STOP_EQUILIBRIUM, FAIL_NAN, MAX_STEPS, BAD_INPUT = range(6)
+FLAG_SECANT_CAP = 0x100
+
+
+class OdeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ode_ensemble error {code}: {msg}")
+        self.code = code
+
+
+class EventSpec(C.Structure):
+    _fields_ = [
+        ("component", C.c_int32), ("direction", C.c_int32), ("stop_after", C.c_int32),
+        ("action_component", C.c_int32), ("action_param", C.c_int32),
+        ("record_component", C.c_int32),
+        ("level", C.c_double), ("tolerance", C.c_double), ("action_coef", C.c_double),
+    ]
+
+
+class AccessorySpec(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("component", C.c_int32)]
+
+
+class Desc(C.Structure):
+    _fields_ = [("model", C.c_int32), ("method", C.c_int32), ("precision", C.c_int32),
+                ("block_size", C.c_int32)]
+
+
+class SolveArgs(C.Structure):
+    _fields_ = [
+        ("n_systems", C.c_int64), ("ld", C.c_int64),
+        ("time_domain", C.c_void_p), ("state", C.c_void_p), ("params", C.c_void_p),
+        ("accessories", C.c_void_p), ("next_h", C.c_void_p), ("status", C.c_void_p),
+        ("counts", C.c_void_p), ("event_counts", C.c_void_p), ("event_records", C.c_void_p),
+        ("system_index", C.c_void_p),
+        ("rtol", C.c_double * MAX_STATE), ("atol", C.c_double * MAX_STATE),
+        ("h0", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
+        ("grow", C.c_double), ("shrink", C.c_double), ("t_record", C.c_double),
+        ("max_steps", C.c_int64), ("max_equilibrium_steps", C.c_int32),
+        ("n_events", C.c_int32), ("n_accessories", C.c_int32),
+        ("event_record_capacity", C.c_int32),
+        ("events", EventSpec * MAX_EVENTS), ("accessory_specs", AccessorySpec * MAX_ACC),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("compute_units", C.c_int32), ("max_grid", C.c_int32),
+                ("resident_systems", C.c_int64)]
+
+
+EXPORTS = ("ode_ensemble_model_dims", "ode_ensemble_create", "ode_ensemble_solve",
+           "ode_ensemble_query", "ode_ensemble_destroy", "ode_ensemble_last_error")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OdeError(ENOTSUP, f"HIP library not built: {path} (run __graft_entry__.build())")
+    L = C.CDLL(path)
+    L.ode_ensemble_model_dims.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.ode_ensemble_model_dims.restype = C.c_int
+    L.ode_ensemble_create.argtypes = [C.POINTER(Desc), C.POINTER(C.c_void_p)]
+    L.ode_ensemble_create.restype = C.c_int
+    L.ode_ensemble_solve.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_void_p]
+    L.ode_ensemble_solve.restype = C.c_int
+    L.ode_ensemble_query.argtypes = [C.c_void_p, C.POINTER(Info)]
+    L.ode_ensemble_query.restype = C.c_int
+    L.ode_ensemble_destroy.argtypes = [C.c_void_p]
+    L.ode_ensemble_destroy.restype = None
+    L.ode_ensemble_last_error.argtypes = []
+    L.ode_ensemble_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise OdeError(rc, load_library().ode_ensemble_last_error().decode())
+
+
+def model_dims(model: str) -> tuple[int, int]:
+    ns, np_ = C.c_int32(), C.c_int32()
+    _check(load_library().ode_ensemble_model_dims(MODEL[model], C.byref(ns), C.byref(np_)))
+    return ns.value, np_.value
+
+
+def _ptr(t, dtype, rows: int, ld: int, name: str):
+    """Device pointer of a [rows, ld] tensor after checking it really is one."""
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor")
+    if t.numel() < rows * ld:
+        raise ValueError(f"{name}: has {t.numel()} elements, needs {rows}*{ld}")
+    if rows > 1 and (t.dim() != 2 or t.shape[1] != ld):
+        raise ValueError(f"{name}: expected shape [{rows}, {ld}], got {tuple(t.shape)}")
+    del torch
+    return t.data_ptr()
+
+
+def fill_args(args: SolveArgs, n_state: int, *, h0: float, rtol=1e-10, atol=1e-10,
+              h_min: float = 1e-12, h_max: float = 1e6, grow: float = 5.0, shrink: float = 0.1,
+              t_record: float = float("-inf"), max_steps: int = 10**8,
+              max_equilibrium_steps: int = 0, events: Sequence[dict] = (),
+              accessories: Sequence[tuple] = (), record_cap: int = 0) -> None:
+    """Scalar options and specs of one solve (paper Sec. 6.4-6.7)."""
+    rt = list(rtol) if hasattr(rtol, "__len__") else [rtol] * n_state
+    at = list(atol) if hasattr(atol, "__len__") else [atol] * n_state
+    for i in range(n_state):
+        args.rtol[i], args.atol[i] = float(rt[i]), float(at[i])
+    args.h0, args.h_min, args.h_max = float(h0), float(h_min), float(h_max)
+    args.grow, args.shrink, args.t_record = float(grow), float(shrink), float(t_record)
+    args.max_steps, args.max_equilibrium_steps = int(max_steps), int(max_equilibrium_steps)
+    if len(events) > MAX_EVENTS or len(accessories) > MAX_ACC:
+        raise ValueError("too many events or accessories")
+    args.n_events, args.n_accessories = len(events), len(accessories)
+    args.event_record_capacity = int(record_cap)
+    for j, e in enumerate(events):
+        ev = args.events[j]
+        ev.component = e["component"]
+        ev.direction = e.get("direction", 0)
+        ev.stop_after = e.get("stop_after", 0)
+        ev.action_component = e.get("action_component", -1)
+        ev.action_param = e.get("action_param", -1)
+        ev.record_component = e.get("record_component", -1)
+        ev.level = e.get("level", 0.0)
+        ev.tolerance = e.get("tolerance", 1e-6)
+        ev.action_coef = e.get("action_coef", 1.0)
+    for k, (kind, comp) in enumerate(accessories):
+        args.accessory_specs[k].kind = ACC_KIND[kind]
+        args.accessory_specs[k].component = comp
+
+
+class Ensemble:
+    """A solver handle for one (model, method, precision) on the current
+    device (paper Sec. 6.2)."""
+
+    def __init__(self, model: str, method: str, precision: str = "fp64", block_size: int = 0):
+        L = load_library()
+        self.model, self.method = model, method
+        self.n_state, self.n_param = model_dims(model)
+        d = Desc(MODEL[model], METHOD[method], PRECISION.get(precision, -1), block_size)
+        h = C.c_void_p()
+        _check(L.ode_ensemble_create(C.byref(d), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ode_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = Info()
+        _check(load_library().ode_ensemble_query(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def outputs(self, ld: int, *, n_accessories: int = 0, n_events: int = 0, record_cap: int = 0,
+                device=None) -> dict:
+        """Freshly allocated output tensors for a solve of leading dimension ld."""
+        import torch
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        out = {
+            "status": torch.full((ld,), -1, dtype=torch.int32, device=dev),
+            "counts": torch.zeros((3, ld), dtype=torch.int64, device=dev),
+            "acc": torch.full((2 * n_accessories, ld), float("nan"), dtype=torch.float64,
+                              device=dev) if n_accessories else None,
+            "event_counts": torch.zeros((n_events, ld), dtype=torch.int32, device=dev)
+            if n_events else None,
+            "event_records": torch.full((record_cap, 2, ld), float("nan"), dtype=torch.float64,
+                                        device=dev) if record_cap else None,
+        }
+        return out
+
+    def solve(self, time_domain, state, params, *, next_h=None, system_index=None, out=None,
+              stream=None, **options: Any) -> dict:
+        """Enqueue one integration on ``stream`` (default: torch's current
+        stream) and return the output tensors (written asynchronously).
+
+        ``time_domain`` [2, ld], ``state`` [n_state, ld] and ``next_h`` [ld]
+        are updated in place; ``params`` [n_param, ld] is read.  Options:
+        h0, rtol, atol, h_min, h_max, grow, shrink, t_record, max_steps,
+        max_equilibrium_steps, events, accessories, record_cap.
+        """
+        import torch
+        ld = int(time_domain.shape[-1])
+        events = list(options.get("events", ()))
+        accs = list(options.get("accessories", ()))
+        cap = int(options.get("record_cap", 0)) if any(
+            e.get("record_component", -1) >= 0 for e in events) else 0
+        options = dict(options, record_cap=cap)
+        if out is None:
+            out = self.outputs(ld, n_accessories=len(accs), n_events=len(events), record_cap=cap,
+                               device=time_domain.device)
+        n = ld if system_index is None else int(system_index.numel())
+        a = SolveArgs()
+        a.n_systems, a.ld = n, ld
+        f64, i32, i64 = torch.float64, torch.int32, torch.int64
+        a.time_domain = _ptr(time_domain, f64, 2, ld, "time_domain")
+        a.state = _ptr(state, f64, self.n_state, ld, "state")
+        a.params = _ptr(params, f64, self.n_param, ld, "params")
+        a.accessories = _ptr(out["acc"], f64, 2 * len(accs), ld, "acc") if accs else None
+        a.next_h = _ptr(next_h, f64, 1, ld, "next_h")
+        a.status = _ptr(out["status"], i32, 1, ld, "status")
+        a.counts = _ptr(out["counts"], i64, 3, ld, "counts") if out.get("counts") is not None else None
+        a.event_counts = (_ptr(out["event_counts"], i32, len(events), ld, "event_counts")
+                          if events else None)
+        if cap:
+            rec = out["event_records"]
+            if rec is None or rec.numel() < cap * 2 * ld or not rec.is_contiguous():
+                raise ValueError("event_records: need a contiguous [cap, 2, ld] float64 tensor")
+            a.event_records = rec.data_ptr()
+        if system_index is not None:
+            if system_index.dtype != i64 or not system_index.is_cuda or not system_index.is_contiguous():
+                raise ValueError("system_index: need a contiguous int64 CUDA tensor")
+            a.system_index = system_index.data_ptr() if n else None
+        fill_args(a, self.n_state, **options)
+        if stream is None:
+            stream = torch.cuda.current_stream(time_domain.device)
+        _check(load_library().ode_ensemble_solve(self._h, C.byref(a), C.c_void_p(stream.cuda_stream)))
+        return out
+
+
+def solve_problem(pb, *, device="cuda", block_size: int = 0, stream=None, ens=None):
+    """Copy a seeded ``inputs.Problem`` to the device, solve it, and return
+    (time_domain, state, outputs) as CUDA tensors (asynchronously written)."""
+    import torch
+    td = torch.as_tensor(pb.time_domain, device=device).contiguous()
+    y = torch.as_tensor(pb.state, device=device).contiguous()
+    p = torch.as_tensor(pb.params, device=device).contiguous()
+    ens = ens or Ensemble(pb.model, pb.method, block_size=block_size)
+    out = ens.solve(td, y, p, stream=stream, **pb.options)
+    return td, y, out

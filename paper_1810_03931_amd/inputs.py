@@ -125,7 +125,7 @@ def duffing_rk4_sweep(n: int = 1024) -> Problem:
     T = TWO_PI
     td = np.stack([np.zeros(n), np.full(n, 96 * T)])
     opts = dict(h0=T / 200.0, t_record=64 * T, accessories=[("max", 0), ("min", 0)],
-                max_steps=10**8)
+                max_steps=2 * 10**7)
     return Problem("duffing_rk4", "duffing", "rk4", td, state, params, opts)
 
 
@@ -150,7 +150,7 @@ def duffing_rkck45_sweep(n_k: int = 512, n_B: int = 256) -> Problem:
     ev = dict(component=1, level=0.0, direction=-1, tolerance=1e-6, stop_after=0,
               record_component=0)
     opts = dict(h0=1e-3, rtol=1e-10, atol=1e-10, h_min=1e-12, h_max=1e6, grow=5.0, shrink=0.1,
-                t_record=1024 * T, events=[ev], record_cap=256, max_steps=10**8)
+                t_record=1024 * T, events=[ev], record_cap=256, max_steps=2 * 10**7)
     return Problem("duffing_rkck45", "duffing", "rkck45", td, state, params, opts)
 
 
@@ -178,7 +178,7 @@ def keller_miksis_sweep(n: int = 1 << 18, *, cluster: bool = True) -> Problem:
     state = np.stack([np.ones(n), np.zeros(n)])
     td = np.stack([np.zeros(n), np.full(n, 128.0)])
     opts = dict(h0=1e-4, rtol=1e-10, atol=1e-10, h_min=1e-12, h_max=1e6, grow=5.0, shrink=0.1,
-                t_record=96.0, accessories=[("max", 0), ("min", 0)], max_steps=10**8)
+                t_record=96.0, accessories=[("max", 0), ("min", 0)], max_steps=2 * 10**7)
     pb = Problem("keller_miksis", "keller_miksis", "rkck45", td, state, params, opts)
     pb.physical = dict(R_E=R_E, P_A1=P_A1, P_A2=P_A2, f1=f1, f2=f2)  # type: ignore[attr-defined]
     return pb
@@ -203,7 +203,7 @@ def relief_valve_sweep(n: int = 1 << 17) -> Problem:
               action_component=1, action_coef=-1.0, action_param=4)
     opts = dict(h0=1e-3, rtol=1e-10, atol=1e-10, h_min=1e-12, h_max=1e6, grow=5.0, shrink=0.1,
                 t_record=1024 * T, events=[ev], accessories=[("max", 0), ("min", 0)],
-                max_steps=10**8)
+                max_steps=2 * 10**7)
     return Problem("relief_valve", "relief_valve", "rkck45", td, state, params, opts)
 
 

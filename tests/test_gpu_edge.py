@@ -1,0 +1,195 @@
+"""Edge cases, failure paths and scheduling invariance of the HIP integrator,
+each checked against the oracle (and, where one exists, a closed form)."""
+import math
+
+import numpy as np
+import pytest
+
+from _parity import compare, run_gpu, run_oracle, take
+from paper_1810_03931_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(model, method, td, y, p, **opts):
+    return I.Problem("edge", model, method, np.ascontiguousarray(td, dtype=np.float64),
+                     np.ascontiguousarray(y, dtype=np.float64),
+                     np.ascontiguousarray(p, dtype=np.float64), opts)
+
+
+def test_empty_solve_is_a_no_op(ode):
+    import torch
+    ens = ode.Ensemble("duffing", "rkck45")
+    td = torch.zeros((2, 0), dtype=torch.float64, device="cuda")
+    y = torch.zeros((2, 0), dtype=torch.float64, device="cuda")
+    p = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+    out = ens.solve(td, y, p, h0=1e-3)
+    torch.cuda.synchronize()
+    assert out["status"].numel() == 0
+
+
+def test_single_system_and_padding_untouched(ode, oracle):
+    import torch
+    pb = I.short_horizon(I.duffing_rkck45_sweep()).subset([12345])
+    ld = 7
+    td = np.full((2, ld), -7.0); td[:, :1] = pb.time_domain
+    y = np.full((2, ld), -7.0); y[:, :1] = pb.state
+    p = np.full((5, ld), -7.0); p[:, :1] = pb.params
+    dev = torch.device("cuda", 0)
+    tdt, yt, pt = (torch.as_tensor(a, device=dev) for a in (td, y, p))
+    ens = ode.Ensemble("duffing", "rkck45")
+    out = ens.solve(tdt, yt, pt, system_index=torch.zeros(1, dtype=torch.int64, device=dev),
+                    **pb.options)
+    torch.cuda.synchronize()
+    assert np.all(tdt.cpu().numpy()[:, 1:] == -7.0) and np.all(yt.cpu().numpy()[:, 1:] == -7.0)
+    assert np.all(out["status"].cpu().numpy()[1:] == -1)
+    o = run_oracle(pb)
+    assert out["status"][0].item() == 0
+    assert np.allclose(yt.cpu().numpy()[:, 0], o["y"][:, 0], rtol=1e-11, atol=1e-11)
+
+
+def test_gather_index_subset_and_invalid_entries(ode, oracle):
+    pb = I.short_horizon(I.relief_valve_sweep(4096))
+    rng = np.random.default_rng(5)
+    chosen = rng.choice(pb.n, 700, replace=False)
+    index = np.concatenate([chosen[:350], [-1, pb.n, 10**9], chosen[350:]])
+    g = run_gpu(pb, index=index)
+    o = run_oracle(pb.subset(chosen))
+    st = compare(take(g, chosen), o, label="gather")
+    untouched = np.setdiff1d(np.arange(pb.n), chosen)
+    assert np.all(g["status"][untouched] == -1)
+    assert np.array_equal(g["y"][:, untouched], pb.state[:, untouched])
+    print("[edge] gather", st)
+
+
+def test_degenerate_time_domains_and_bad_input(ode, oracle):
+    n = 6
+    td = np.array([[0.0, 1.0, 5.0, np.nan, 0.0, 0.0], [1.0, 1.0, 4.0, 1.0, np.inf, 2.0]])
+    y = np.tile([[0.3], [0.1]], (1, n))
+    p = np.tile([[0.1], [0.5], [1.0], [1.0], [1.0]], (1, n))
+    pb = _problem("duffing", "rkck45", td, y, p, h0=1e-3, accessories=[("max", 0)])
+    g, o = run_gpu(pb), run_oracle(pb)
+    assert list(o["status"]) == [0, 0, 0, 5, 5, 0]
+    compare(g, o, label="degenerate")
+    assert np.all(g["counts"][:, 1:5] == 0)
+
+
+def test_nan_at_minimum_step_and_step_budget(ode, oracle):
+    td = np.array([[0.0, 0.0], [1.0, 50.0]])
+    y = np.array([[0.1, 0.1], [0.0, 0.0], [-1.0, 10.0]])
+    p = np.tile([[1.25], [10.0], [20.0], [5.0], [0.8]], (1, 2))
+    pb = _problem("relief_valve", "rkck45", td, y, p, h0=1e-2, h_min=1e-6, max_steps=37)
+    g, o = run_gpu(pb), run_oracle(pb)
+    assert list(o["status"]) == [3, 4]
+    compare(g, o, label="nan/budget")
+    assert g["counts"][:, 1].sum() == 37
+
+
+def test_bouncing_ball_against_closed_form(ode, oracle):
+    """Ballistic bounces with restitution 0.8 stop at the 6th impact: times
+    follow t_{n+1} = t_n + 2 r^n v1 / g."""
+    g_acc, r_c, tol, n_b = 2.0, 0.8, 1e-11, 6
+    n = 64
+    h0s = np.linspace(0.5, 2.0, n)
+    td = np.stack([np.zeros(n), np.full(n, 100.0)])
+    y = np.stack([h0s, np.zeros(n)])
+    p = np.full((1, n), g_acc)
+    ev = dict(component=0, level=0.0, direction=-1, tolerance=tol, stop_after=n_b,
+              action_component=1, action_coef=-r_c, record_component=0)
+    pb = _problem("ballistic", "rkck45", td, y, p, h0=1e-2, h_max=0.05, t_record=0.0,
+                  events=[ev], record_cap=8)
+    g, o = run_gpu(pb), run_oracle(pb)
+    compare(g, o, label="ballistic")
+    v1 = np.sqrt(2 * g_acc * h0s)
+    t = [np.sqrt(2 * h0s / g_acc)]
+    for m in range(1, n_b):
+        t.append(t[-1] + 2 * r_c**m * v1 / g_acc)
+    assert np.all(g["status"] == 1)
+    assert np.max(np.abs(g["event_records"][:n_b, 0] - np.array(t))) <= 1e-9
+
+
+def test_equilibrium_stop_and_rk4_landing(ode, oracle):
+    td = np.array([[0.0], [1e4]])
+    y = np.array([[0.0], [0.0], [10.0]])
+    p = np.array([[1.25], [10.0], [20.0], [10.0], [0.8]])
+    pb = _problem("relief_valve", "rkck45", td, y, p, h0=1e-3, max_equilibrium_steps=50,
+                  events=[dict(component=1, direction=-1, tolerance=1e-6)])
+    g, o = run_gpu(pb), run_oracle(pb)
+    assert o["status"][0] == 2
+    compare(g, o, label="equilibrium")
+    # RK4 lands exactly in the zone of y = 1 - t^2 at t = 1: no location
+    pb = _problem("ballistic", "rk4", np.array([[0.0], [10.0]]), np.array([[1.0], [0.0]]),
+                  np.array([[2.0]]), h0=0.25,
+                  events=[dict(component=0, direction=-1, tolerance=1e-12, stop_after=1)])
+    g, o = run_gpu(pb), run_oracle(pb)
+    compare(g, o, label="rk4 landing")
+    assert g["t"][0] == 1.0 and g["counts"][2, 0] == 0
+
+
+def test_record_overflow_and_multiple_events(ode, oracle):
+    pb = I.short_horizon(I.duffing_rkck45_sweep()).subset(np.arange(0, 2**17, 97))
+    pb.time_domain[1] = 12 * 2 * math.pi
+    pb.options.update(record_cap=3, events=[
+        dict(component=1, direction=-1, tolerance=1e-6, record_component=0),
+        dict(component=0, level=0.5, direction=0, tolerance=1e-8),
+        dict(component=1, direction=1, tolerance=1e-6, stop_after=9)])
+    g, o = run_gpu(pb), run_oracle(pb)
+    st = compare(g, o, label="multi-event")
+    assert np.any(o["event_counts"][0] > 3)
+    print("[edge] multi-event", st)
+
+
+def test_resume_in_two_solves(ode, oracle):
+    """Final time into t0 and next_h make a second solve continue (paper
+    Sec. 6.8); the split run matches the oracle's split run."""
+    import torch
+    pb = I.short_horizon(I.keller_miksis_sweep(2048))
+    T = pb.time_domain[1].copy()
+    dev = torch.device("cuda", 0)
+    td = torch.as_tensor(pb.time_domain, device=dev).clone()
+    y = torch.as_tensor(pb.state, device=dev).clone()
+    p = torch.as_tensor(pb.params, device=dev)
+    hn = torch.zeros(pb.n, dtype=torch.float64, device=dev)
+    ens = ode.Ensemble(pb.model, pb.method)
+    tdo, yo, hno = pb.time_domain.copy(), pb.state.copy(), np.zeros(pb.n)
+    from oracle import oracle as O
+    for frac in (0.5, 1.0):
+        td[1] = torch.as_tensor(T * frac, device=dev)
+        tdo[1] = T * frac
+        ens.solve(td, y, p, next_h=hn, **pb.options)
+        O.solve(pb.model, pb.method, tdo, yo, pb.params, next_h=hno, **pb.options)
+    torch.cuda.synchronize()
+    scale = np.max(np.abs(yo), axis=0)
+    assert np.all(np.abs(y.cpu().numpy() - yo) <= 1e-10 * scale)
+    assert np.array_equal(td[0].cpu().numpy(), tdo[0])
+
+
+# ---- scheduling invariance: results are bitwise identical however the
+# ---- systems are grouped into lanes, waves and workgroups
+
+def _bitwise_equal(a, b, idx_a=None):
+    for k in ("status", "counts", "y", "t", "acc", "event_counts", "event_records"):
+        x = a[k] if idx_a is None else take(a, idx_a)[k]
+        assert np.array_equal(x, b[k], equal_nan=True), k
+
+
+def test_invariance_block_size_permutation_and_mix(ode):
+    pb = I.short_horizon(I.relief_valve_sweep(1 << 15))
+    ref = run_gpu(pb, block_size=256)
+    _bitwise_equal(ref, run_gpu(pb, block_size=64))
+    perm = np.random.default_rng(0).permutation(pb.n)
+    _bitwise_equal(ref, run_gpu(pb.subset(perm)), idx_a=perm)
+    alone = pb.subset([777])
+    _bitwise_equal(ref, run_gpu(alone), idx_a=[777])
+
+
+def test_repeated_solves_reuse_the_queue(ode):
+    """The work-queue counters reset themselves after every launch: three
+    back-to-back solves on one handle integrate every system each time."""
+    pb = I.short_horizon(I.duffing_rkck45_sweep(64, 64))
+    ens = ode.Ensemble(pb.model, pb.method)
+    first = run_gpu(pb, ens=ens)
+    for _ in range(2):
+        again = run_gpu(pb, ens=ens)
+        _bitwise_equal(first, again)
+    assert np.all(first["status"] == 0)
