@@ -56,35 +56,89 @@ def parse():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--uniform", type=int, default=-1, metavar="SYSTEM",
+                    help="give every system the parameters and initial state of SYSTEM, so all "
+                         "lanes step in lockstep (FLOP-per-attempt calibration with counters)")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the kernel sources and exit")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes):
+    """A plain device-to-device copy of known size: what HBM byte counters read
+    for it scales the integrator's counter readings to bytes."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                      "launches": 3}), flush=True)
 
 
 def cpu_baseline(pb, target_s):
     """The oracle, as it is, on a stratified sample of the same sweep over the
-    full horizon, on all host cores; accepted system-steps/s."""
+    full horizon, on all host cores; accepted system-steps/s.  The sample
+    grows until one run takes at least half of target_s."""
     from oracle import oracle as O
     from paper_1810_03931_amd import inputs as I
-    cores = os.cpu_count() or 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    pilot = pb.subset(I.stratified_sample(pb.n, 2 * threads, seed=21))
-    t0 = time.perf_counter()
-    O.solve(pilot.model, pilot.method, pilot.time_domain.copy(), pilot.state.copy(),
-            pilot.params, threads=threads, **pilot.options)
-    per_sys = (time.perf_counter() - t0) / pilot.n
-    k = int(min(pb.n, max(2 * threads, target_s / max(per_sys, 1e-9))))
-    sample = pb.subset(I.stratified_sample(pb.n, k, seed=22))
-    t0 = time.perf_counter()
-    r = O.solve(sample.model, sample.method, sample.time_domain.copy(), sample.state.copy(),
-                sample.params, threads=threads, **sample.options)
-    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    k = min(pb.n, 4 * threads)
+    while True:
+        sample = pb.subset(I.stratified_sample(pb.n, k, seed=22))
+        t0 = time.perf_counter()
+        r = O.solve(sample.model, sample.method, sample.time_domain.copy(), sample.state.copy(),
+                    sample.params, threads=threads, **sample.options)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_s or k >= pb.n:
+            break
+        k = int(min(pb.n, max(2 * k, k * target_s / max(dt, 1e-3))))
     acc = int(r["counts"][0].sum())
     return {"value": acc / dt, "unit": "system-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{k} of {pb.n} systems (stratified), full horizon, {acc} accepted steps "
                       f"in {dt:.1f} s"}
 
 
+def kernel_source_hash():
+    """Hash of the integrator's sources: counter readings taken for another
+    version of the kernel are not reported."""
+    import hashlib
+    from paper_1810_03931_amd import build
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(build.CSRC)):
+        with open(os.path.join(build.CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    h.update(" ".join(build.FLAGS[:-4]).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter summary of this
+    workload, if it was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return float(vals["bytes_per_launch"])
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the systems are independent and this build "
               "measures the single-GPU kernel (see the design notes for how it would shard).",
@@ -100,6 +154,10 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     pb = I.CONFIGS[args.config]()
+    if args.uniform >= 0:
+        pb.params[:] = pb.params[:, args.uniform:args.uniform + 1]
+        pb.state[:] = pb.state[:, args.uniform:args.uniform + 1]
+        pb.time_domain[:] = pb.time_domain[:, args.uniform:args.uniform + 1]
     ens = E.Ensemble(pb.model, pb.method, block_size=args.block_size)
     td0 = torch.as_tensor(pb.time_domain, device=dev).contiguous()
     y0 = torch.as_tensor(pb.state, device=dev).contiguous()
@@ -154,7 +212,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded parameter sweep)",
-        "config": {"workload": pb.name, "systems": pb.n, "model": pb.model, "method": pb.method,
+        "config": {"workload": pb.name + ("/uniform" if args.uniform >= 0 else ""), "systems": pb.n, "model": pb.model, "method": pb.method,
                    "horizon": float(pb.time_domain[1, 0]), "t_record": pb.options.get("t_record"),
                    "rtol": pb.options.get("rtol"), "block_size": info["block_size"],
                    "resident_systems": info["resident_systems"]},
@@ -165,7 +223,8 @@ def main():
         "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
         "kernel_ms": float(kernel_ms.mean()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(pb.name) if args.uniform < 0 else None,
                      "flops_per_attempt": flops_attempt, "attempts_per_launch": attempts},
     }
     if not args.no_cpu_baseline:

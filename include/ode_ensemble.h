@@ -194,7 +194,8 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out);
  * final state, final time into t0 (so a second call continues, Sec. 6.8),
  * next step, status, counts, accessories, event counts and records.
  * Arguments are validated before anything is enqueued (ODE_EINVAL); a HIP
- * launch failure returns ODE_EHIP.  One handle must not run two solves at
+ * launch failure returns ODE_EHIP.  With n_systems == 0 nothing is read,
+ * written or launched, and the array pointers may be NULL.  One handle must not run two solves at
  * the same time; separate handles may run concurrently. */
 int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *args, void *hip_stream);
 

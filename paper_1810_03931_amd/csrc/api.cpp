@@ -203,17 +203,18 @@ static int validate(const ode_ensemble *e, const ode_solve_args *a) {
                 (long long)a->n_systems);
   }
   if (a->ld > (int64_t(1) << 40)) return fail(ODE_EINVAL, "ld too large");
-  if (!a->time_domain || !a->state || !a->status)
+  const bool work = a->n_systems > 0;  // with no systems nothing is read or written
+  if (work && (!a->time_domain || !a->state || !a->status))
     return fail(ODE_EINVAL, "time_domain, state and status are required");
-  if (np > 0 && !a->params) return fail(ODE_EINVAL, "params is required");
+  if (work && np > 0 && !a->params) return fail(ODE_EINVAL, "params is required");
   if (a->n_events < 0 || a->n_events > ODE_MAX_EVENTS)
     return fail(ODE_EINVAL, "n_events must be in [0, %d]", ODE_MAX_EVENTS);
   if (a->n_accessories < 0 || a->n_accessories > ODE_MAX_ACCESSORIES)
     return fail(ODE_EINVAL, "n_accessories must be in [0, %d]", ODE_MAX_ACCESSORIES);
-  if (a->n_accessories > 0 && !a->accessories)
+  if (work && a->n_accessories > 0 && !a->accessories)
     return fail(ODE_EINVAL, "accessories array is NULL but n_accessories > 0");
   if (a->event_record_capacity < 0) return fail(ODE_EINVAL, "event_record_capacity < 0");
-  if ((a->event_record_capacity > 0) != (a->event_records != nullptr))
+  if (work && (a->event_record_capacity > 0) != (a->event_records != nullptr))
     return fail(ODE_EINVAL, "event_records must be given exactly when the capacity is > 0");
   if (!finite_pos(a->h0)) return fail(ODE_EINVAL, "h0 must be finite and > 0");
   if (a->max_steps < 1 || a->max_steps > ODE_MAX_STEPS_LIMIT)

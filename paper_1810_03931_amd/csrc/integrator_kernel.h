@@ -73,36 +73,42 @@ __device__ __forceinline__ double stage_time(double t, double c, double h) {
 }
 
 // One Cash-Karp step of length h from (t, y): propagated fifth-order
-// solution y5 and error estimate err = h * sum e_i k_i.
+// solution y5 and error estimate err = h * sum e_i k_i.  The time-only terms
+// of all six stages are evaluated first.
 template <class M>
 __device__ __forceinline__ void cash_karp_attempt(double t, const double (&y)[M::NS],
                                                   const double (&p)[M::NP], double h,
                                                   double (&y5)[M::NS], double (&err)[M::NS]) {
   constexpr int N = M::NS;
+  constexpr int FW = M::NF > 0 ? M::NF : 1;
+  const double ts[6] = {t, stage_time(t, ck::c2, h), stage_time(t, ck::c3, h),
+                        stage_time(t, ck::c4, h), t + h, stage_time(t, ck::c6, h)};
+  double F[6][FW];
+  M::template forcing<6>(ts, p, F);
   double k1[N], k2[N], k3[N], k4[N], k5[N], k6[N], ys[N];
-  M::rhs(t, y, p, k1);
+  M::rhs(y, p, F[0], k1);
 #pragma unroll
   for (int i = 0; i < N; ++i) ys[i] = fma(h, ck::a21 * k1[i], y[i]);
-  M::rhs(stage_time(t, ck::c2, h), ys, p, k2);
+  M::rhs(ys, p, F[1], k2);
 #pragma unroll
   for (int i = 0; i < N; ++i) ys[i] = fma(h, fma(ck::a32, k2[i], ck::a31 * k1[i]), y[i]);
-  M::rhs(stage_time(t, ck::c3, h), ys, p, k3);
+  M::rhs(ys, p, F[2], k3);
 #pragma unroll
   for (int i = 0; i < N; ++i)
     ys[i] = fma(h, fma(ck::a43, k3[i], fma(ck::a42, k2[i], ck::a41 * k1[i])), y[i]);
-  M::rhs(stage_time(t, ck::c4, h), ys, p, k4);
+  M::rhs(ys, p, F[3], k4);
 #pragma unroll
   for (int i = 0; i < N; ++i)
     ys[i] = fma(h, fma(ck::a54, k4[i], fma(ck::a53, k3[i], fma(ck::a52, k2[i], ck::a51 * k1[i]))),
                 y[i]);
-  M::rhs(t + h, ys, p, k5);
+  M::rhs(ys, p, F[4], k5);
 #pragma unroll
   for (int i = 0; i < N; ++i)
     ys[i] = fma(h,
                 fma(ck::a65, k5[i],
                     fma(ck::a64, k4[i], fma(ck::a63, k3[i], fma(ck::a62, k2[i], ck::a61 * k1[i])))),
                 y[i]);
-  M::rhs(stage_time(t, ck::c6, h), ys, p, k6);
+  M::rhs(ys, p, F[5], k6);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     y5[i] = fma(h, fma(ck::b6, k6[i], fma(ck::b4, k4[i], fma(ck::b3, k3[i], ck::b1 * k1[i]))), y[i]);
@@ -117,21 +123,43 @@ __device__ __forceinline__ void rk4_attempt(double t, const double (&y)[M::NS],
                                             const double (&p)[M::NP], double h,
                                             double (&yn)[M::NS]) {
   constexpr int N = M::NS;
-  double k1[N], k2[N], k3[N], k4[N], ys[N];
+  constexpr int FW = M::NF > 0 ? M::NF : 1;
   const double hh = 0.5 * h;
-  M::rhs(t, y, p, k1);
+  const double ts[3] = {t, t + hh, t + h};
+  double F[3][FW];
+  M::template forcing<3>(ts, p, F);
+  double k1[N], k2[N], k3[N], k4[N], ys[N];
+  M::rhs(y, p, F[0], k1);
 #pragma unroll
   for (int i = 0; i < N; ++i) ys[i] = fma(hh, k1[i], y[i]);
-  M::rhs(t + hh, ys, p, k2);
+  M::rhs(ys, p, F[1], k2);
 #pragma unroll
   for (int i = 0; i < N; ++i) ys[i] = fma(hh, k2[i], y[i]);
-  M::rhs(t + hh, ys, p, k3);
+  M::rhs(ys, p, F[1], k3);
 #pragma unroll
   for (int i = 0; i < N; ++i) ys[i] = fma(h, k3[i], y[i]);
-  M::rhs(t + h, ys, p, k4);
+  M::rhs(ys, p, F[2], k4);
   const double h6 = h * (1.0 / 6.0);
 #pragma unroll
   for (int i = 0; i < N; ++i) yn[i] = fma(h6, fma(2.0, k2[i] + k3[i], k1[i] + k4[i]), y[i]);
+}
+
+// E^(-1/5) for the step-size factor.  A single-precision seed (hardware
+// log2/exp2, ~1e-7 relative) is refined by two Newton steps on x^-5 = E,
+// x <- x + x (1 - E x^5) / 5, whose error goes 1e-7 -> 3e-14 -> rounding;
+// outside [1e-30, 1e30] (where the factor is clamped anyway) the library
+// routine is used.
+__device__ __forceinline__ double inv_fifth_root(double E) {
+  if (!(E >= 1e-30 && E <= 1e30)) return pow(E, -0.2);
+  const float lf = __builtin_amdgcn_logf(static_cast<float>(E));
+  double x = static_cast<double>(__builtin_amdgcn_exp2f(-0.2f * lf));
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double x2 = x * x;
+    const double x5 = x2 * x2 * x;
+    x = fma(x * 0.2, fma(-E, x5, 1.0), x);
+  }
+  return x;
 }
 
 // Event detection between the last accepted point (Fo, outside the zone) and
@@ -364,7 +392,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, cons
             ++n_rej;
           }
         } else {
-          double fac = (E == 0.0) ? c.grow : 0.9 * pow(E, -0.2);
+          double fac = (E == 0.0) ? c.grow : 0.9 * inv_fifth_root(E);
           fac = fmax(c.shrink, fmin(c.grow, fac));
           h_next = fmax(c.h_min, fmin(c.h_max, fac * h_att));
           if (!(E <= 1.0) && h_att > c.h_min) {

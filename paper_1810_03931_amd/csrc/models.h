@@ -3,49 +3,130 @@
 // per model and the right-hand side is inlined into the stage loop (the paper
 // keeps its device functions in the kernel's translation unit for the same
 // reason, Sec. 6.9).
+//
+// The right-hand side is split in two: `forcing` evaluates the terms that
+// depend on time only (the harmonic excitations) at all stage times of one
+// attempt, before the stage chain starts, and `rhs` combines them with the
+// state.  The time-only terms are then independent work the scheduler can
+// overlap with the dependent stage chain, and the stage values can be formed
+// from one full sine/cosine evaluation per attempt by angle addition.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace odeens {
 
+// sin and cos of (base + delta) from sb = sin(base), cb = cos(base), for
+// |delta| <= pi/4.  sin(delta) and cos(delta) - 1 are their Taylor series
+// through delta^15 / delta^16 (truncation below 1e-16 relative on the
+// interval); cos(delta) - 1 is formed directly so that nothing cancels.
+__device__ __forceinline__ void rotate(double delta, double sb, double cb, double &s, double &c) {
+  const double d2 = delta * delta;
+  double ps = -1.0 / 1307674368000.0;        // -1/15!
+  ps = fma(ps, d2, 1.0 / 6227020800.0);      //  1/13!
+  ps = fma(ps, d2, -1.0 / 39916800.0);       // -1/11!
+  ps = fma(ps, d2, 1.0 / 362880.0);          //  1/9!
+  ps = fma(ps, d2, -1.0 / 5040.0);           // -1/7!
+  ps = fma(ps, d2, 1.0 / 120.0);             //  1/5!
+  ps = fma(ps, d2, -1.0 / 6.0);              // -1/3!
+  const double sd = fma(delta * d2, ps, delta);
+  double pc = 1.0 / 20922789888000.0;        //  1/16!
+  pc = fma(pc, d2, -1.0 / 87178291200.0);    // -1/14!
+  pc = fma(pc, d2, 1.0 / 479001600.0);       //  1/12!
+  pc = fma(pc, d2, -1.0 / 3628800.0);        // -1/10!
+  pc = fma(pc, d2, 1.0 / 40320.0);           //  1/8!
+  pc = fma(pc, d2, -1.0 / 720.0);            // -1/6!
+  pc = fma(pc, d2, 1.0 / 24.0);              //  1/4!
+  pc = fma(pc, d2, -0.5);                    // -1/2!
+  const double cm1 = d2 * pc;
+  s = fma(cb, sd, fma(sb, cm1, sb));
+  c = fma(cb, cm1, fma(-sb, sd, cb));
+}
+
+// sin/cos of `arg` given sin/cos of a nearby `base`.  The difference
+// arg - base is exact when the two are within a factor of two (Sterbenz), so
+// the function is evaluated at exactly `arg`; far from `base` (a long step)
+// the full library routine is used.
+__device__ __forceinline__ void sincos_near(double arg, double base, double sb, double cb,
+                                            double &s, double &c) {
+  constexpr double kQuarterPi = 0.78539816339744830962;
+  const double delta = __dsub_rn(arg, base);
+  if (fabs(delta) <= kQuarterPi) {
+    rotate(delta, sb, cb, s, c);
+  } else {
+    sincos(arg, &s, &c);
+  }
+}
+
 // Duffing oscillator, paper Sec. 2.1 Eqs. (1)-(2), with linear and cubic
 // stiffness as parameters: p = (k, B, omega, lin, cub),
 //   y1' = y2,  y2' = -lin*y1 - cub*y1^3 - k*y2 + B*cos(omega*t).
+// Time-only term per stage: cos(omega*t).
 struct Duffing {
   static constexpr int NS = 2;
   static constexpr int NP = 5;
+  static constexpr int NF = 1;
   static constexpr int ID = 1;
-  __device__ __forceinline__ static void rhs(double t, const double (&y)[NS], const double (&p)[NP],
-                                             double (&f)[NS]) {
+  template <int S>
+  __device__ __forceinline__ static void forcing(const double (&ts)[S], const double (&p)[NP],
+                                                 double (&F)[S][NF]) {
+    const double base = p[2] * ts[0];
+    double sb, cb;
+    sincos(base, &sb, &cb);
+    F[0][0] = cb;
+#pragma unroll
+    for (int k = 1; k < S; ++k) {
+      double s, c;
+      sincos_near(__dmul_rn(p[2], ts[k]), base, sb, cb, s, c);
+      F[k][0] = c;
+    }
+  }
+  __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&p)[NP],
+                                             const double (&F)[NF], double (&f)[NS]) {
     const double y1 = y[0], y2 = y[1];
-    const double forcing = p[1] * cos(p[2] * t);
     const double spring = fma(p[4] * y1 * y1, y1, fma(p[3], y1, p[0] * y2));
     f[0] = y2;
-    f[1] = forcing - spring;
+    f[1] = fma(p[1], F[0], -spring);
   }
 };
 
 // Keller-Miksis bubble model in the paper's dimensionless form, Sec. 2.2
 // (numerator N_KM, denominator D_KM, coefficients C0..C12); t is tau.
+// Time-only terms per stage: sin and cos of 2*pi*tau and of
+// 2*pi*C11*tau + C12, each phase rounded as the plain expression is.
 struct KellerMiksis {
   static constexpr int NS = 2;
   static constexpr int NP = 13;
+  static constexpr int NF = 4;
   static constexpr int ID = 2;
-  __device__ __forceinline__ static void rhs(double tau, const double (&y)[NS],
-                                             const double (&C)[NP], double (&f)[NS]) {
+  template <int S>
+  __device__ __forceinline__ static void forcing(const double (&ts)[S], const double (&C)[NP],
+                                                 double (&F)[S][NF]) {
     constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const double w2 = __dmul_rn(kTwoPi, C[11]);
+    const double b1 = kTwoPi * ts[0];
+    const double b2 = __dadd_rn(__dmul_rn(w2, ts[0]), C[12]);
+    double s1b, c1b, s2b, c2b;
+    sincos(b1, &s1b, &c1b);
+    sincos(b2, &s2b, &c2b);
+    F[0][0] = s1b;
+    F[0][1] = c1b;
+    F[0][2] = s2b;
+    F[0][3] = c2b;
+#pragma unroll
+    for (int k = 1; k < S; ++k) {
+      sincos_near(__dmul_rn(kTwoPi, ts[k]), b1, s1b, c1b, F[k][0], F[k][1]);
+      sincos_near(__dadd_rn(__dmul_rn(w2, ts[k]), C[12]), b2, s2b, c2b, F[k][2], F[k][3]);
+    }
+  }
+  __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&C)[NP],
+                                             const double (&F)[NF], double (&f)[NS]) {
     const double y1 = y[0], y2 = y[1];
     const double rx = 1.0 / y1;
     const double gas = pow(rx, C[10]);
-    double s1, c1, s2, c2;
-    sincos(kTwoPi * tau, &s1, &c1);
-    // phase 2*pi*C11*tau + C12 rounded as written: |phase| reaches ~1e5, where
-    // one ulp of difference would already move sin/cos by ~1e-11
-    sincos(__dadd_rn(__dmul_rn(__dmul_rn(kTwoPi, C[11]), tau), C[12]), &s2, &c2);
-    const double u = fma(C[9], y2, 1.0);                 // 1 + C9*y2
-    const double forcing_p = fma(C[5], s1, C[6] * s2);   // C5 sin + C6 sin
-    const double forcing_d = fma(C[7], c1, C[8] * c2);   // C7 cos + C8 cos
+    const double u = fma(C[9], y2, 1.0);                     // 1 + C9*y2
+    const double forcing_p = fma(C[5], F[0], C[6] * F[2]);   // C5 sin + C6 sin
+    const double forcing_d = fma(C[7], F[1], C[8] * F[3]);   // C7 cos + C8 cos
     const double inertia = fma(-C[9] * (1.0 / 3.0), y2, 1.0) * 1.5 * y2 * y2;
     double N = fma(C[1], y2, C[0]) * gas;
     N = fma(-C[2], u, N);
@@ -64,9 +145,13 @@ struct KellerMiksis {
 struct ReliefValve {
   static constexpr int NS = 3;
   static constexpr int NP = 5;
+  static constexpr int NF = 0;
   static constexpr int ID = 3;
-  __device__ __forceinline__ static void rhs(double, const double (&y)[NS], const double (&p)[NP],
-                                             double (&f)[NS]) {
+  template <int S>
+  __device__ __forceinline__ static void forcing(const double (&)[S], const double (&)[NP],
+                                                 double (&)[S][1]) {}
+  __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&p)[NP],
+                                             const double (&)[1], double (&f)[NS]) {
     f[0] = y[1];
     f[1] = fma(-p[0], y[1], y[2] - (y[0] + p[1]));
     f[2] = p[2] * fma(-y[0], sqrt(y[2]), p[3]);
@@ -77,9 +162,13 @@ struct ReliefValve {
 struct Ballistic {
   static constexpr int NS = 2;
   static constexpr int NP = 1;
+  static constexpr int NF = 0;
   static constexpr int ID = 4;
-  __device__ __forceinline__ static void rhs(double, const double (&y)[NS], const double (&p)[NP],
-                                             double (&f)[NS]) {
+  template <int S>
+  __device__ __forceinline__ static void forcing(const double (&)[S], const double (&)[NP],
+                                                 double (&)[S][1]) {}
+  __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&p)[NP],
+                                             const double (&)[1], double (&f)[NS]) {
     f[0] = y[1];
     f[1] = -p[0];
   }

@@ -8,13 +8,30 @@ that pass through zero (a velocity at a turning point) are judged against
 the state's magnitude, as the integrator's own error control does.  Integer
 outputs (status, step counts, event counts) must be identical.
 
+Conditioning: some systems amplify rounding-level differences far beyond
+1e-11 within a short horizon (near-Zeno impact chatter of the relief valve,
+violent bubble collapses); for them the plain definition itself fixes the
+answer only to the precision the problem's conditioning allows.  `floor`
+measures that per system with the oracle alone: twin oracle runs whose
+initial state is moved by 1e-15 * max(1, |y0|) (two sign patterns).  A system
+passes when it agrees within max(1e-11, 100 * floor).  The factor was
+calibrated on the CPU: the oracle rebuilt with FMA contraction (rounding
+differences at every operation, as on the GPU) stays within 19 * floor on
+the worst of 2000 systems of every sweep (p99 <= 6 * floor).
+Well-conditioned systems are held to 1e-11.  Systems whose twins already
+change their step counts are decision-fragile and are compared like flips.
+
 A "decision flip" is a system whose accept/reject sequence differs between
 the two sides: both compute the same formulas, but libm and the GPU's math
 library may differ in the last bit of cos/sin/pow, and if an error estimate
 lands within that rounding of the acceptance threshold the two sides take
 different (equally valid) steps.  Such systems are identified by unequal
 step counts, reported, bounded in number, and compared against the looser
-bound their different-but-valid step sequences imply.
+bound their different-but-valid step sequences imply: on the same
+calibration, flips and fragile systems stay within 2e-5 of each other (they
+are violent bubble collapses amplifying 1e-15 by 1e9 and more) and make up
+under 1% of the Keller-Miksis sweep and none of the others; they must stay
+within max(1e-3, 100 * floor) and under 1% of the systems.
 """
 from __future__ import annotations
 
@@ -52,6 +69,52 @@ def run_gpu(pb, *, block_size: int = 0, index=None, ens=None) -> dict:
     return r
 
 
+def adiff(a, b):
+    """|a - b| where NaN on both sides counts as equal and NaN on one side as
+    infinitely far."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    with np.errstate(invalid="ignore"):
+        d = np.abs(a - b)
+    d = np.where(np.isnan(a) & np.isnan(b), 0.0, d)
+    return np.where(np.isnan(d), np.inf, d)
+
+
+def oracle_with_floor(pb, threads: int = 0):
+    """Oracle result, per-system conditioning floor and decision-fragile mask."""
+    o = run_oracle(pb, threads)
+    scale = np.maximum(np.max(np.abs(np.nan_to_num(o["y"])), axis=0), 1e-300)
+    tscale = np.maximum(np.abs(o["t1"]), 1.0)
+    floor = np.zeros(pb.n)
+    fragile = np.zeros(pb.n, dtype=bool)
+    ns = pb.state.shape[0]
+    size = np.maximum(np.max(np.abs(pb.state), axis=0), 1.0)
+    for pattern in (np.ones(ns), (-1.0) ** np.arange(ns)):
+        tw = pb.copy()
+        tw.state = tw.state + 1e-15 * pattern[:, None] * size[None, :]
+        ot = run_oracle(tw, threads)
+        fragile |= ~np.all(ot["counts"] == o["counts"], axis=0)
+        fragile |= ot["status"] != o["status"]
+        d = np.max(adiff(ot["y"], o["y"]), axis=0) / scale
+        d = np.maximum(d, adiff(ot["t"], o["t"]) / tscale)
+        if o["acc"].shape[0]:
+            d = np.maximum(d, np.max(adiff(ot["acc"][0::2], o["acc"][0::2]), axis=0) / scale)
+            d = np.maximum(d, np.max(adiff(ot["acc"][1::2], o["acc"][1::2]), axis=0) / tscale)
+        if o["event_records"].shape[0]:
+            rec = adiff(ot["event_records"], o["event_records"])
+            d = np.maximum(d, np.max(rec[:, 0], axis=0) / tscale)
+            d = np.maximum(d, np.max(rec[:, 1], axis=0) / scale)
+            fragile |= ~np.all(ot["event_counts"] == o["event_counts"], axis=0)
+        floor = np.maximum(floor, np.where(np.isfinite(d), d, 0.0))
+        fragile |= ~np.isfinite(d)
+    return o, floor, fragile
+
+
+def check(pb, g, *, label: str = "", **kw) -> dict:
+    """Oracle run with conditioning floor, then compare with GPU result g."""
+    o, floor, fragile = oracle_with_floor(pb)
+    return compare(g, o, floor=floor, fragile=fragile, label=label, **kw)
+
+
 def take(r: dict, idx) -> dict:
     """The systems idx of a result (columns of every array)."""
     idx = np.asarray(idx)
@@ -69,35 +132,53 @@ def take(r: dict, idx) -> dict:
 
 
 def rel_err(a, b, scale):
-    return np.abs(a - b) / np.maximum(np.maximum(np.abs(b), scale), 1e-300)
+    return adiff(a, b) / np.maximum(np.maximum(np.abs(np.nan_to_num(b)), scale), 1e-300)
 
 
-def compare(g: dict, o: dict, *, rel: float = 1e-11, max_flip_frac: float = 1e-3,
-            flip_rel: float = 1e-5, label: str = "") -> dict:
-    """Element-wise parity of a GPU result g with the oracle result o."""
+def compare(g: dict, o: dict, *, rel: float = 1e-11, floor=None, fragile=None,
+            max_flip_frac: float = 0.01, flip_rel: float = 1e-3, label: str = "") -> dict:
+    """Element-wise parity of a GPU result g with the oracle result o
+    (floor, fragile: from oracle_with_floor)."""
     n = o["y"].shape[1]
-    assert np.array_equal(g["status"], o["status"]), \
+    if floor is None:
+        floor = np.zeros(n)
+    if fragile is None:
+        fragile = np.zeros(n, dtype=bool)
+    steady = ~fragile
+    assert np.array_equal(g["status"][steady], o["status"][steady]), \
         f"{label}: status differs on {np.sum(g['status'] != o['status'])} systems"
-    same_steps = np.all(g["counts"] == o["counts"], axis=0)
-    flips = np.flatnonzero(~same_steps)
-    scale = np.max(np.abs(o["y"]), axis=0)                       # per system
+    same_steps = np.all(g["counts"] == o["counts"], axis=0) & steady
+    flips = np.flatnonzero(~same_steps & steady)
+    loose = ~same_steps                                   # flips and fragile systems
+    bar = np.maximum(rel, 100.0 * floor)                  # per system
+    scale = np.max(np.abs(np.nan_to_num(o["y"])), axis=0)  # per system
     ey = rel_err(g["y"], o["y"], scale[None, :])
     tscale = np.maximum(np.abs(o["t1"]), 1.0)
-    et = np.abs(g["t"] - o["t"]) / tscale
-    stats = {"n": n, "flips": len(flips), "max_rel_y": float(ey[:, same_steps].max(initial=0)),
+    et = adiff(g["t"], o["t"]) / tscale
+    stats = {"n": n, "flips": len(flips), "fragile": int(fragile.sum()),
+             "ill_conditioned": int(np.sum(floor > 1e-13)),   # amplification > 100
+             "max_rel_y_well": float(ey[:, same_steps & (bar == rel)].max(initial=0)),
+             "max_rel_y": float(ey[:, same_steps].max(initial=0)),
              "max_rel_t": float(et[same_steps].max(initial=0))}
-    assert len(flips) <= max(1, int(max_flip_frac * n)), f"{label}: {len(flips)} decision flips"
-    bad = np.flatnonzero(same_steps & (np.any(ey > rel, axis=0) | (et > rel)))
-    assert bad.size == 0, (f"{label}: {bad.size} systems beyond {rel}: first {bad[:5]}, "
-                           f"max {ey.max():.3e}")
-    if flips.size:
-        assert np.all(ey[:, flips] <= flip_rel), f"{label}: flip systems beyond {flip_rel}"
+    assert len(flips) + int(fragile.sum()) <= max(1, int(max_flip_frac * n)), \
+        f"{label}: {len(flips)} decision flips, {int(fragile.sum())} fragile systems"
+    bad = np.flatnonzero(same_steps & (np.any(ey > bar[None, :], axis=0) | (et > bar)))
+    assert bad.size == 0, (f"{label}: {bad.size} systems beyond their bar: first {bad[:5]}, "
+                           f"err {ey[:, bad[:5]].max(axis=0)}, bar {bar[bad[:5]]}")
+    if loose.any():
+        loose_bar = np.maximum(flip_rel, 100.0 * floor)
+        worst = float(ey[:, loose].max())
+        stats["max_rel_y_loose"] = worst
+        assert np.all(ey[:, loose] <= loose_bar[None, loose]), \
+            f"{label}: flip/fragile systems beyond max({flip_rel}, 100*floor): {worst:.3e}"
+        assert np.all(np.isfinite(g["y"][:, loose]) == np.isfinite(o["y"][:, loose]))
     na = o["acc"].shape[0] // 2
     if na:
         av = rel_err(g["acc"][0::2], o["acc"][0::2], scale[None, :])
-        at = np.abs(g["acc"][1::2] - o["acc"][1::2]) / tscale[None, :]
+        at = adiff(g["acc"][1::2], o["acc"][1::2]) / tscale[None, :]
         stats["max_rel_acc"] = float(av[:, same_steps].max(initial=0))
-        bad = np.flatnonzero(same_steps & (np.any(av > rel, axis=0) | np.any(at > rel, axis=0)))
+        bad = np.flatnonzero(same_steps & (np.any(av > bar[None, :], axis=0)
+                                           | np.any(at > bar[None, :], axis=0)))
         assert bad.size == 0, f"{label}: accessories differ on {bad.size} systems: {bad[:5]}"
     ne = o["event_counts"].shape[0]
     if ne:
@@ -110,8 +191,9 @@ def compare(g: dict, o: dict, *, rel: float = 1e-11, max_flip_frac: float = 1e-3
                                   ~np.isnan(g["event_records"][:, 0])[:, same_steps]), \
                 f"{label}: different record slots written"
             mask = filled & same_steps[None, :]
-            rt = np.abs(g["event_records"][:, 0] - o["event_records"][:, 0]) / tscale[None, :]
+            rt = adiff(g["event_records"][:, 0], o["event_records"][:, 0]) / tscale[None, :]
             rv = rel_err(g["event_records"][:, 1], o["event_records"][:, 1], scale[None, :])
             stats["max_rel_rec"] = float(np.where(mask, np.maximum(rt, rv), 0).max(initial=0))
-            assert np.all(np.where(mask, np.maximum(rt, rv), 0) <= rel), f"{label}: records differ"
+            assert np.all(np.where(mask, np.maximum(rt, rv), 0) <= bar[None, :]), \
+                f"{label}: records differ"
     return stats

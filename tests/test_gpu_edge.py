@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from _parity import compare, run_gpu, run_oracle, take
+from _parity import check, compare, oracle_with_floor, run_gpu, run_oracle, take
 from paper_1810_03931_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -54,8 +54,8 @@ def test_gather_index_subset_and_invalid_entries(ode, oracle):
     chosen = rng.choice(pb.n, 700, replace=False)
     index = np.concatenate([chosen[:350], [-1, pb.n, 10**9], chosen[350:]])
     g = run_gpu(pb, index=index)
-    o = run_oracle(pb.subset(chosen))
-    st = compare(take(g, chosen), o, label="gather")
+    o, floor, fragile = oracle_with_floor(pb.subset(chosen))
+    st = compare(take(g, chosen), o, floor=floor, fragile=fragile, label="gather")
     untouched = np.setdiff1d(np.arange(pb.n), chosen)
     assert np.all(g["status"][untouched] == -1)
     assert np.array_equal(g["y"][:, untouched], pb.state[:, untouched])
@@ -70,7 +70,7 @@ def test_degenerate_time_domains_and_bad_input(ode, oracle):
     pb = _problem("duffing", "rkck45", td, y, p, h0=1e-3, accessories=[("max", 0)])
     g, o = run_gpu(pb), run_oracle(pb)
     assert list(o["status"]) == [0, 0, 0, 5, 5, 0]
-    compare(g, o, label="degenerate")
+    check(pb, g, label="degenerate")
     assert np.all(g["counts"][:, 1:5] == 0)
 
 
@@ -81,7 +81,7 @@ def test_nan_at_minimum_step_and_step_budget(ode, oracle):
     pb = _problem("relief_valve", "rkck45", td, y, p, h0=1e-2, h_min=1e-6, max_steps=37)
     g, o = run_gpu(pb), run_oracle(pb)
     assert list(o["status"]) == [3, 4]
-    compare(g, o, label="nan/budget")
+    check(pb, g, label="nan/budget")
     assert g["counts"][:, 1].sum() == 37
 
 
@@ -98,8 +98,8 @@ def test_bouncing_ball_against_closed_form(ode, oracle):
               action_component=1, action_coef=-r_c, record_component=0)
     pb = _problem("ballistic", "rkck45", td, y, p, h0=1e-2, h_max=0.05, t_record=0.0,
                   events=[ev], record_cap=8)
-    g, o = run_gpu(pb), run_oracle(pb)
-    compare(g, o, label="ballistic")
+    g = run_gpu(pb)
+    check(pb, g, label="ballistic")
     v1 = np.sqrt(2 * g_acc * h0s)
     t = [np.sqrt(2 * h0s / g_acc)]
     for m in range(1, n_b):
@@ -116,13 +116,13 @@ def test_equilibrium_stop_and_rk4_landing(ode, oracle):
                   events=[dict(component=1, direction=-1, tolerance=1e-6)])
     g, o = run_gpu(pb), run_oracle(pb)
     assert o["status"][0] == 2
-    compare(g, o, label="equilibrium")
+    check(pb, g, label="equilibrium")
     # RK4 lands exactly in the zone of y = 1 - t^2 at t = 1: no location
     pb = _problem("ballistic", "rk4", np.array([[0.0], [10.0]]), np.array([[1.0], [0.0]]),
                   np.array([[2.0]]), h0=0.25,
                   events=[dict(component=0, direction=-1, tolerance=1e-12, stop_after=1)])
-    g, o = run_gpu(pb), run_oracle(pb)
-    compare(g, o, label="rk4 landing")
+    g = run_gpu(pb)
+    check(pb, g, label="rk4 landing")
     assert g["t"][0] == 1.0 and g["counts"][2, 0] == 0
 
 
@@ -133,17 +133,20 @@ def test_record_overflow_and_multiple_events(ode, oracle):
         dict(component=1, direction=-1, tolerance=1e-6, record_component=0),
         dict(component=0, level=0.5, direction=0, tolerance=1e-8),
         dict(component=1, direction=1, tolerance=1e-6, stop_after=9)])
-    g, o = run_gpu(pb), run_oracle(pb)
-    st = compare(g, o, label="multi-event")
+    g = run_gpu(pb)
+    o, floor, fragile = oracle_with_floor(pb)
+    st = compare(g, o, floor=floor, fragile=fragile, label="multi-event")
     assert np.any(o["event_counts"][0] > 3)
     print("[edge] multi-event", st)
 
 
 def test_resume_in_two_solves(ode, oracle):
     """Final time into t0 and next_h make a second solve continue (paper
-    Sec. 6.8); the split run matches the oracle's split run."""
+    Sec. 6.8); the split run matches the oracle's split run.  (Duffing: its
+    short-horizon conditioning floor stays below 1e-12, so 1e-10 is a tight
+    bar; Keller-Miksis lanes may amplify rounding far more.)"""
     import torch
-    pb = I.short_horizon(I.keller_miksis_sweep(2048))
+    pb = I.short_horizon(I.duffing_rkck45_sweep()).subset(np.arange(0, 1 << 17, 64))
     T = pb.time_domain[1].copy()
     dev = torch.device("cuda", 0)
     td = torch.as_tensor(pb.time_domain, device=dev).clone()
