@@ -27,23 +27,23 @@ sys.path.insert(0, ROOT)
 METRIC = "system-steps/s + % FP64 VALU peak (RKCK45 sweep); p50/p99 sweep latency"
 FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
 
-# Algorithmic FP64 operations per attempted step (FMA = 2, add/mul/div/sqrt = 1)
-# counted from the method and the model's right-hand side, plus the number of
-# transcendental calls per attempt (cos, sin/cos pairs, pow); the FLOP value
-# of one call is TRANS_FLOPS (a minimax polynomial of the libm kind).
-ARITH_PER_ATTEMPT = {
-    ("duffing", "rkck45"): 131 + 6 * 10,
-    ("duffing", "rk4"): 30 + 4 * 10,
-    ("keller_miksis", "rkck45"): 131 + 6 * 38,
-    ("relief_valve", "rkck45"): 183 + 6 * 9,
+# FP64 FLOP per attempted step of one system (the roofline's per-unit figure).
+# Calibrated with hardware counters on a lock-step input (bench.py --uniform S:
+# every lane has the parameters of system S, so no lane is masked):
+#   FLOP = 64*(ADD + MUL + TRANS) + 128*FMA of SQ_INSTS_VALU_*_F64, / attempts.
+# The figure includes the FP64 work the math library does inside cos/sin/pow.
+# Source: profiles/<workload>_fp64_counters.txt ("uniform" block).  Workloads
+# without a calibration fall back to a count from the formulas (FMA = 2,
+# add/mul/div/sqrt = 1) plus 40 FLOP per library transcendental.
+FLOPS_PER_ATTEMPT = {
+    "duffing_rkck45": (466.7, "counter calibration, uniform lanes"),
 }
-TRANS_PER_ATTEMPT = {
-    ("duffing", "rkck45"): 6 + 1,
-    ("duffing", "rk4"): 4,
-    ("keller_miksis", "rkck45"): 6 * 3 + 1,
-    ("relief_valve", "rkck45"): 1,
+FLOPS_ESTIMATE = {
+    ("duffing", "rk4"): 70 + 4 * 40,
+    ("duffing", "rkck45"): 191 + 7 * 40,
+    ("keller_miksis", "rkck45"): 359 + 19 * 40,
+    ("relief_valve", "rkck45"): 237 + 7 * 40,
 }
-TRANS_FLOPS = 40
 
 
 def parse():
@@ -196,14 +196,15 @@ def main():
     total_ms = s0.elapsed_time(s1)
     kernel_ms = np.array([a.elapsed_time(b) for a, b in kernel_events])
 
+    per_system = out["counts"].sum(dim=0).cpu().numpy()     # attempts of each system
     counts = out["counts"].sum(dim=1).cpu().numpy()        # accepted, rejected, location
     status = np.bincount(out["status"].cpu().numpy() & 0xFF, minlength=6)
     accepted, attempts = int(counts[0]), int(counts.sum())
     ms_per_step = total_ms / args.steps
     value = accepted / (ms_per_step / 1e3)
 
-    key = (pb.model, pb.method)
-    flops_attempt = ARITH_PER_ATTEMPT[key] + TRANS_PER_ATTEMPT[key] * TRANS_FLOPS
+    flops_attempt, flops_src = FLOPS_PER_ATTEMPT.get(
+        pb.name, (FLOPS_ESTIMATE[(pb.model, pb.method)], "estimate from the formulas"))
     kern_s = float(kernel_ms.mean()) / 1e3
     achieved = attempts * flops_attempt / kern_s / 1e12
     info = ens.info()
@@ -219,13 +220,17 @@ def main():
         "attempted_steps_per_s": attempts / (ms_per_step / 1e3),
         "reject_frac": float(counts[1] / attempts), "location_frac": float(counts[2] / attempts),
         "status_counts": status.tolist(),
+        "attempts_per_system": {"p50": float(np.percentile(per_system, 50)),
+                                "p99": float(np.percentile(per_system, 99)),
+                                "max": int(per_system.max())},
         "p50_ms": float(np.percentile(np.array(wall) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
         "kernel_ms": float(kernel_ms.mean()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": measured_traffic(pb.name) if args.uniform < 0 else None,
-                     "flops_per_attempt": flops_attempt, "attempts_per_launch": attempts},
+                     "flops_per_attempt": flops_attempt, "flops_per_attempt_source": flops_src,
+                     "attempts_per_launch": attempts},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)

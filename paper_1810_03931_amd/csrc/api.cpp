@@ -29,13 +29,12 @@ const void *integrator_kernel(int model, int method, int nev, int nacc) {
   }
 }
 
-hipError_t launch_integrator(int model, int method, int nev, int nacc, const Control &c,
-                             const Arrays &a, int grid, int block, hipStream_t stream) {
+hipError_t launch_integrator(int model, int method, int nev, int nacc, const Params &prm,
+                             int grid, int block, hipStream_t stream) {
   const void *fn = integrator_kernel(model, method, nev, nacc);
   if (!fn) return hipErrorInvalidDeviceFunction;
-  Control cc = c;
-  Arrays aa = a;
-  void *args[] = {&cc, &aa};
+  Params pp = prm;
+  void *args[] = {&pp};
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, stream);
 }
 }  // namespace odeens
@@ -268,8 +267,9 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   if (rc != ODE_OK) return rc;
   if (a->n_systems == 0) return ODE_OK;
 
-  Control c;
-  std::memset(&c, 0, sizeof c);
+  Params prm;
+  std::memset(&prm, 0, sizeof prm);
+  Control &c = prm.c;
   for (int i = 0; i < ODE_MAX_STATE; ++i) {
     c.rtol[i] = a->rtol[i];
     c.atol[i] = a->atol[i];
@@ -302,7 +302,7 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   const int64_t need = (a->n_systems + e->block - 1) / e->block;
   const int grid = static_cast<int>(need < max_grid ? need : max_grid);
 
-  Arrays arr;
+  Arrays &arr = prm.a;
   arr.td = a->time_domain;
   arr.y = a->state;
   arr.p = a->params;
@@ -318,7 +318,7 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   arr.queue = e->queue;
   arr.total_waves = static_cast<uint32_t>(grid) * static_cast<uint32_t>(e->block / 64);
 
-  hipError_t err = launch_integrator(e->model, e->method, nev, nacc, c, arr, grid, e->block,
+  hipError_t err = launch_integrator(e->model, e->method, nev, nacc, prm, grid, e->block,
                                      static_cast<hipStream_t>(hip_stream));
   if (err != hipSuccess) return hip_fail(err, "integrator launch");
   e->last_blocks_per_cu = bpc;

@@ -64,6 +64,12 @@ struct Arrays {
   uint32_t total_waves;
 };
 
+// Everything one launch needs, passed as the single by-value kernel argument.
+struct Params {
+  Control c;
+  Arrays a;
+};
+
 // Compile-time variants: number of event / accessory slots compiled in.
 inline int event_slots(int n_events) { return n_events == 0 ? 0 : (n_events == 1 ? 1 : 4); }
 inline int acc_slots(int n_acc) { return n_acc == 0 ? 0 : (n_acc <= 2 ? 2 : 4); }
@@ -72,7 +78,7 @@ inline int acc_slots(int n_acc) { return n_acc == 0 ? 0 : (n_acc <= 2 ? 2 : 4); 
 const void *integrator_kernel(int model, int method, int nev, int nacc);
 
 // Launch it with `grid` workgroups of `block` threads on `stream`.
-hipError_t launch_integrator(int model, int method, int nev, int nacc, const Control &c,
-                             const Arrays &a, int grid, int block, hipStream_t stream);
+hipError_t launch_integrator(int model, int method, int nev, int nacc, const Params &prm,
+                             int grid, int block, hipStream_t stream);
 
 }  // namespace odeens

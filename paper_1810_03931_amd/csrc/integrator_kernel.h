@@ -183,14 +183,62 @@ __device__ __forceinline__ double secant(double sa, double ga, double sb, double
   return (sc > lo && sc < hi) ? sc : __dmul_rn(0.5, __dadd_rn(lo, hi));
 }
 
+// The launch parameters seen through an opaque copy of the kernel-argument
+// pointer.  Values read through it are loaded where they are used (scalar
+// loads), instead of being hoisted to the kernel start and held in scalar
+// registers for the whole run: the array pointers and the rarely used event
+// fields would otherwise exhaust the scalar register file and spill into
+// vector-register lanes inside the hot loop.
+typedef const __attribute__((address_space(4))) Params *ParamsRef;
+__device__ __forceinline__ ParamsRef fresh_params() {
+  ParamsRef p = (ParamsRef)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Field-wise copies out of the kernel-argument segment (the implicit copy
+// constructors cannot bind to its address space).
+__device__ __forceinline__ Arrays arrays_of(ParamsRef q) {
+  Arrays a;
+  a.td = q->a.td;
+  a.y = q->a.y;
+  a.p = q->a.p;
+  a.acc = q->a.acc;
+  a.next_h = q->a.next_h;
+  a.status = q->a.status;
+  a.counts = q->a.counts;
+  a.evc = q->a.evc;
+  a.rec = q->a.rec;
+  a.index = q->a.index;
+  a.n = q->a.n;
+  a.ld = q->a.ld;
+  a.queue = q->a.queue;
+  a.total_waves = q->a.total_waves;
+  return a;
+}
+
+__device__ __forceinline__ EventCtl event_of(ParamsRef q, int j) {
+  EventCtl e;
+  e.component = q->c.ev[j].component;
+  e.direction = q->c.ev[j].direction;
+  e.stop_after = q->c.ev[j].stop_after;
+  e.action_component = q->c.ev[j].action_component;
+  e.action_param = q->c.ev[j].action_param;
+  e.record_component = q->c.ev[j].record_component;
+  e.level = q->c.ev[j].level;
+  e.tolerance = q->c.ev[j].tolerance;
+  e.action_coef = q->c.ev[j].action_coef;
+  return e;
+}
+
 template <class M, int METHOD, int NEV, int NACC>
-__global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, const Arrays a) {
+__global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
+  const Control &c = prm.c;
   constexpr int N = M::NS;
   constexpr int P = M::NP;
   constexpr int EV = NEV > 0 ? NEV : 1;
   constexpr int AC = NACC > 0 ? NACC : 1;
   const int lane = threadIdx.x & 63;
-  const int64_t ld = a.ld;
 
   // ---- per-lane system state (registers) ----
   int64_t s = -1;
@@ -235,6 +283,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, cons
 
   auto retire = [&]() {
     if (!window_open) acc_init();  // window never opened: describe the final point
+    const ParamsRef q = fresh_params();
+    const Arrays a = arrays_of(q);
+    const int64_t ld = a.ld;
     a.td[s] = t;
 #pragma unroll
     for (int i = 0; i < N; ++i) a.y[i * ld + s] = y[i];
@@ -263,6 +314,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, cons
     // ---- refill idle lanes from the queue (all 64 lanes are converged here) ----
     const unsigned long long need = __ballot(!active);
     if (need != 0 && !exhausted) {
+      const ParamsRef q = fresh_params();
+      const Arrays a = arrays_of(q);
+      const int64_t ld = a.ld;
       const uint32_t k = __popcll(need);
       unsigned long long base = 0;
       if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)k);
@@ -272,9 +326,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, cons
       if (!active) {
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-        const unsigned long long q = base + rank;
-        if (q < (unsigned long long)a.n) {
-          const int64_t cand = a.index ? a.index[q] : (int64_t)q;
+        const unsigned long long pos = base + rank;
+        if (pos < (unsigned long long)a.n) {
+          const int64_t cand = a.index ? a.index[pos] : (int64_t)pos;
           if (cand >= 0 && cand < ld) {
             s = cand;
             active = true;
@@ -523,20 +577,24 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, cons
           ++cnt[j];
           if (window_open) {
             ++wcnt[j];
-            if (c.ev[j].record_component >= 0) {
-              if (n_rec < c.rec_cap) {
-                a.rec[(int64_t)(2 * n_rec) * ld + s] = t;
-                a.rec[(int64_t)(2 * n_rec + 1) * ld + s] = pick(y, c.ev[j].record_component);
+            if (fresh_params()->c.ev[j].record_component >= 0) {
+              const ParamsRef q = fresh_params();
+              if (n_rec < q->c.rec_cap) {
+                const int64_t ld = q->a.ld;
+                q->a.rec[(int64_t)(2 * n_rec) * ld + s] = t;
+                q->a.rec[(int64_t)(2 * n_rec + 1) * ld + s] = pick(y, q->c.ev[j].record_component);
               }
               ++n_rec;
             }
           }
-          if (c.ev[j].action_component >= 0) {
-            double coef = c.ev[j].action_coef;
-            if (c.ev[j].action_param >= 0) coef *= pick(p, c.ev[j].action_param);
-            put(y, c.ev[j].action_component, coef * pick(y, c.ev[j].action_component));
+          const ParamsRef q = fresh_params();
+          const EventCtl e = event_of(q, j);
+          if (e.action_component >= 0) {
+            double coef = e.action_coef;
+            if (e.action_param >= 0) coef *= pick(p, e.action_param);
+            put(y, e.action_component, coef * pick(y, e.action_component));
           }
-          if (c.ev[j].stop_after > 0 && cnt[j] == c.ev[j].stop_after) status = kStopEvent;
+          if (e.stop_after > 0 && cnt[j] == e.stop_after) status = kStopEvent;
         }
       }
       // zone states: normal exactly when outside the zone; accepted steps
@@ -568,6 +626,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Control c, cons
 
   // The last wave to leave resets the queue for the next launch.
   if (lane == 0) {
+    const Arrays a = arrays_of(fresh_params());
     __threadfence();
     const unsigned long long done = atomicAdd(a.queue + 1, 1ull);
     if (done + 1 == (unsigned long long)a.total_waves) {
