@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--config", default="duffing_rkck45",
                     choices=["duffing_rk4", "duffing_rkck45", "keller_miksis", "relief_valve"])
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="override rtol = atol of the sweep (0: the sweep's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--uniform", type=int, default=-1, metavar="SYSTEM",
@@ -154,11 +157,13 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     pb = I.CONFIGS[args.config]()
+    if args.tol > 0:
+        pb = I.with_tolerance(pb, args.tol)
     if args.uniform >= 0:
         pb.params[:] = pb.params[:, args.uniform:args.uniform + 1]
         pb.state[:] = pb.state[:, args.uniform:args.uniform + 1]
         pb.time_domain[:] = pb.time_domain[:, args.uniform:args.uniform + 1]
-    ens = E.Ensemble(pb.model, pb.method, block_size=args.block_size)
+    ens = E.Ensemble(pb.model, pb.method, precision=args.precision, block_size=args.block_size)
     td0 = torch.as_tensor(pb.time_domain, device=dev).contiguous()
     y0 = torch.as_tensor(pb.state, device=dev).contiguous()
     p = torch.as_tensor(pb.params, device=dev).contiguous()
@@ -203,19 +208,22 @@ def main():
     ms_per_step = total_ms / args.steps
     value = accepted / (ms_per_step / 1e3)
 
+    key = pb.name if (args.precision == "fp64" and args.tol <= 0) else None
     flops_attempt, flops_src = FLOPS_PER_ATTEMPT.get(
-        pb.name, (FLOPS_ESTIMATE[(pb.model, pb.method)], "estimate from the formulas"))
+        key, (FLOPS_ESTIMATE[(pb.model, pb.method)], "estimate from the formulas"))
     kern_s = float(kernel_ms.mean()) / 1e3
     achieved = attempts * flops_attempt / kern_s / 1e12
     info = ens.info()
     line = {
         "metric": METRIC, "value": value, "unit": "system-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 stages / f64 state",
         "data": "synthetic (seeded parameter sweep)",
         "config": {"workload": pb.name + ("/uniform" if args.uniform >= 0 else ""), "systems": pb.n, "model": pb.model, "method": pb.method,
                    "horizon": float(pb.time_domain[1, 0]), "t_record": pb.options.get("t_record"),
-                   "rtol": pb.options.get("rtol"), "block_size": info["block_size"],
+                   "rtol": pb.options.get("rtol"), "precision": args.precision,
+                   "block_size": info["block_size"],
                    "resident_systems": info["resident_systems"]},
         "attempted_steps_per_s": attempts / (ms_per_step / 1e3),
         "reject_frac": float(counts[1] / attempts), "location_frac": float(counts[2] / attempts),

@@ -64,8 +64,15 @@ enum ode_model {
 /* Integration schemes (paper Sec. 3 and Sec. 6.4). */
 enum ode_method { ODE_RKCK45 = 0, ODE_RK4 = 1 };
 
-/* Arithmetic of the integrator.  FP64 is the paper's (Sec. 6.1). */
-enum ode_precision { ODE_FP64 = 0 };
+/* Arithmetic of the integrator.
+ *   ODE_FP64         everything in binary64, the paper's arithmetic (Sec. 6.1).
+ *   ODE_FP32_STAGES  the right-hand side and the stage sums in binary32; time,
+ *                    step size, error norm, state accumulation, accessories and
+ *                    event location in binary64.  The FP32 rounding of the
+ *                    stage derivatives (~6e-8 relative) sets a noise floor on
+ *                    the error estimate and on the result, so it suits
+ *                    tolerances of about 1e-7 and looser. */
+enum ode_precision { ODE_FP64 = 0, ODE_FP32_STAGES = 1 };
 
 /* Accessory kinds (paper Sec. 5 and Sec. 6.7): a running maximum or minimum
  * of one state component over the recording window, with the time at which

@@ -14,24 +14,24 @@
 #include "integrator.h"
 
 namespace odeens {
-const void *kernels_duffing(int method, int nev, int nacc);
-const void *kernels_keller_miksis(int method, int nev, int nacc);
-const void *kernels_relief_valve(int method, int nev, int nacc);
-const void *kernels_ballistic(int method, int nev, int nacc);
+const void *kernels_duffing(int method, int prec, int nev, int nacc);
+const void *kernels_keller_miksis(int method, int prec, int nev, int nacc);
+const void *kernels_relief_valve(int method, int prec, int nev, int nacc);
+const void *kernels_ballistic(int method, int prec, int nev, int nacc);
 
-const void *integrator_kernel(int model, int method, int nev, int nacc) {
+const void *integrator_kernel(int model, int method, int prec, int nev, int nacc) {
   switch (model) {
-    case ODE_MODEL_DUFFING: return kernels_duffing(method, nev, nacc);
-    case ODE_MODEL_KELLER_MIKSIS: return kernels_keller_miksis(method, nev, nacc);
-    case ODE_MODEL_RELIEF_VALVE: return kernels_relief_valve(method, nev, nacc);
-    case ODE_MODEL_BALLISTIC: return kernels_ballistic(method, nev, nacc);
+    case ODE_MODEL_DUFFING: return kernels_duffing(method, prec, nev, nacc);
+    case ODE_MODEL_KELLER_MIKSIS: return kernels_keller_miksis(method, prec, nev, nacc);
+    case ODE_MODEL_RELIEF_VALVE: return kernels_relief_valve(method, prec, nev, nacc);
+    case ODE_MODEL_BALLISTIC: return kernels_ballistic(method, prec, nev, nacc);
     default: return nullptr;
   }
 }
 
-hipError_t launch_integrator(int model, int method, int nev, int nacc, const Params &prm,
-                             int grid, int block, hipStream_t stream) {
-  const void *fn = integrator_kernel(model, method, nev, nacc);
+hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc,
+                             const Params &prm, int grid, int block, hipStream_t stream) {
+  const void *fn = integrator_kernel(model, method, prec, nev, nacc);
   if (!fn) return hipErrorInvalidDeviceFunction;
   Params pp = prm;
   void *args[] = {&pp};
@@ -111,9 +111,8 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out) {
   if (!model_dims(desc->model, &ns, &np)) return fail(ODE_EINVAL, "unknown model %d", desc->model);
   if (desc->method != ODE_RKCK45 && desc->method != ODE_RK4)
     return fail(ODE_EINVAL, "unknown method %d", desc->method);
-  if (desc->precision != ODE_FP64)
-    return fail(desc->precision == 1 ? ODE_ENOTSUP : ODE_EINVAL, "precision %d not available",
-                desc->precision);
+  if (desc->precision != ODE_FP64 && desc->precision != ODE_FP32_STAGES)
+    return fail(ODE_EINVAL, "unknown precision %d", desc->precision);
   int block = desc->block_size == 0 ? kDefaultBlock : desc->block_size;
   if (block < 64 || block > kMaxBlock || block % 64 != 0)
     return fail(ODE_EINVAL, "block_size %d must be a multiple of 64 in [64, %d]",
@@ -163,7 +162,7 @@ void ode_ensemble_destroy(ode_ensemble *e) {
 static int query_blocks(ode_ensemble *e, int nev, int nacc, int *out) {
   int &slot = e->blocks_per_cu[combo_index(nev, nacc)];
   if (slot == 0) {
-    const void *fn = integrator_kernel(e->model, e->method, nev, nacc);
+    const void *fn = integrator_kernel(e->model, e->method, e->precision, nev, nacc);
     if (!fn) return fail(ODE_ENOTSUP, "no kernel for this model/method");
     int nb = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, e->block, 0);
@@ -318,8 +317,8 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   arr.queue = e->queue;
   arr.total_waves = static_cast<uint32_t>(grid) * static_cast<uint32_t>(e->block / 64);
 
-  hipError_t err = launch_integrator(e->model, e->method, nev, nacc, prm, grid, e->block,
-                                     static_cast<hipStream_t>(hip_stream));
+  hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid,
+                                     e->block, static_cast<hipStream_t>(hip_stream));
   if (err != hipSuccess) return hip_fail(err, "integrator launch");
   e->last_blocks_per_cu = bpc;
   e->last_grid = grid;

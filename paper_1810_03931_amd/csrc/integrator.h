@@ -74,11 +74,12 @@ struct Params {
 inline int event_slots(int n_events) { return n_events == 0 ? 0 : (n_events == 1 ? 1 : 4); }
 inline int acc_slots(int n_acc) { return n_acc == 0 ? 0 : (n_acc <= 2 ? 2 : 4); }
 
-// The kernel for (model, method, event slots, accessory slots), or nullptr.
-const void *integrator_kernel(int model, int method, int nev, int nacc);
+// The kernel for (model, method, precision, event slots, accessory slots), or
+// nullptr.
+const void *integrator_kernel(int model, int method, int prec, int nev, int nacc);
 
 // Launch it with `grid` workgroups of `block` threads on `stream`.
-hipError_t launch_integrator(int model, int method, int nev, int nacc, const Params &prm,
-                             int grid, int block, hipStream_t stream);
+hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc,
+                             const Params &prm, int grid, int block, hipStream_t stream);
 
 }  // namespace odeens

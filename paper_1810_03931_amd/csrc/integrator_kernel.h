@@ -37,7 +37,20 @@ constexpr double e1 = -277.0 / 64512.0, e3 = 6925.0 / 370944.0, e4 = -6925.0 / 2
                  e5 = -277.0 / 14336.0, e6 = 277.0 / 7084.0;
 }  // namespace ck
 
+// The same coefficients rounded to FP32 for the mixed-precision stage sums.
+namespace ckf {
+constexpr float a21 = 1.0f / 5.0f;
+constexpr float a31 = 3.0f / 40.0f, a32 = 9.0f / 40.0f;
+constexpr float a41 = 3.0f / 10.0f, a42 = -9.0f / 10.0f, a43 = 6.0f / 5.0f;
+constexpr float a51 = -11.0f / 54.0f, a52 = 5.0f / 2.0f, a53 = -70.0f / 27.0f, a54 = 35.0f / 27.0f;
+constexpr float a61 = 1631.0f / 55296.0f, a62 = 175.0f / 512.0f, a63 = 575.0f / 13824.0f,
+                a64 = 44275.0f / 110592.0f, a65 = 253.0f / 4096.0f;
+constexpr float b1 = 37.0f / 378.0f, b3 = 250.0f / 621.0f, b4 = 125.0f / 594.0f,
+                b6 = 512.0f / 1771.0f;
+}  // namespace ckf
+
 enum { kMethodRKCK45 = 0, kMethodRK4 = 1 };
+enum { kPrecFP64 = 0, kPrecMixed = 1 };
 
 // y[c] for a component index c known only at run time, as a bitmask blend of
 // all components.  (A chain of selects between array elements is folded by
@@ -115,6 +128,98 @@ __device__ __forceinline__ void cash_karp_attempt(double t, const double (&y)[M:
     err[i] = h * fma(ck::e6, k6[i],
                      fma(ck::e5, k5[i], fma(ck::e4, k4[i], fma(ck::e3, k3[i], ck::e1 * k1[i]))));
   }
+}
+
+// Mixed precision (NEXT-1 of the design): the right-hand side and the stage
+// sums run in FP32, the state, time, step and the error estimate in FP64.
+// Each stage input is y + h * (FP32 sum) formed in FP64 and rounded once to
+// FP32; the propagated solution adds the FP32 weighted sum to y in FP64; the
+// error estimate h * sum e_i k_i is formed in FP64 from the FP32 stage
+// derivatives, so it carries their rounding (~6e-8 relative) but no
+// cancellation.
+template <class M>
+__device__ __forceinline__ void cash_karp_attempt_mixed(double t, const double (&y)[M::NS],
+                                                        const double (&p)[M::NP],
+                                                        const float (&q)[M::NP], double h,
+                                                        double (&y5)[M::NS],
+                                                        double (&err)[M::NS]) {
+  constexpr int N = M::NS;
+  constexpr int FW = M::NF > 0 ? M::NF : 1;
+  const double ts[6] = {t, stage_time(t, ck::c2, h), stage_time(t, ck::c3, h),
+                        stage_time(t, ck::c4, h), t + h, stage_time(t, ck::c6, h)};
+  float F[6][FW];
+  M::template forcing32<6>(ts, p, F);
+  float k1[N], k2[N], k3[N], k4[N], k5[N], k6[N], ys[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(y[i]);
+  M::rhs32(ys, q, F[0], k1);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(h, double(ckf::a21 * k1[i]), y[i]));
+  M::rhs32(ys, q, F[1], k2);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = static_cast<float>(fma(h, double(fmaf(ckf::a32, k2[i], ckf::a31 * k1[i])), y[i]));
+  M::rhs32(ys, q, F[2], k3);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = static_cast<float>(
+        fma(h, double(fmaf(ckf::a43, k3[i], fmaf(ckf::a42, k2[i], ckf::a41 * k1[i]))), y[i]));
+  M::rhs32(ys, q, F[3], k4);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = static_cast<float>(fma(
+        h,
+        double(fmaf(ckf::a54, k4[i], fmaf(ckf::a53, k3[i], fmaf(ckf::a52, k2[i], ckf::a51 * k1[i])))),
+        y[i]));
+  M::rhs32(ys, q, F[4], k5);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    ys[i] = static_cast<float>(fma(
+        h,
+        double(fmaf(ckf::a65, k5[i],
+                    fmaf(ckf::a64, k4[i],
+                         fmaf(ckf::a63, k3[i], fmaf(ckf::a62, k2[i], ckf::a61 * k1[i]))))),
+        y[i]));
+  M::rhs32(ys, q, F[5], k6);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float inc = fmaf(ckf::b6, k6[i], fmaf(ckf::b4, k4[i], fmaf(ckf::b3, k3[i], ckf::b1 * k1[i])));
+    y5[i] = fma(h, double(inc), y[i]);
+    err[i] = h * fma(ck::e6, double(k6[i]),
+                     fma(ck::e5, double(k5[i]),
+                         fma(ck::e4, double(k4[i]), fma(ck::e3, double(k3[i]), ck::e1 * double(k1[i])))));
+  }
+}
+
+// Classical RK4 with FP32 right-hand side and stage sums, FP64 state.
+template <class M>
+__device__ __forceinline__ void rk4_attempt_mixed(double t, const double (&y)[M::NS],
+                                                  const double (&p)[M::NP],
+                                                  const float (&q)[M::NP], double h,
+                                                  double (&yn)[M::NS]) {
+  constexpr int N = M::NS;
+  constexpr int FW = M::NF > 0 ? M::NF : 1;
+  const double hh = 0.5 * h;
+  const double ts[3] = {t, t + hh, t + h};
+  float F[3][FW];
+  M::template forcing32<3>(ts, p, F);
+  float k1[N], k2[N], k3[N], k4[N], ys[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(y[i]);
+  M::rhs32(ys, q, F[0], k1);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(hh, double(k1[i]), y[i]));
+  M::rhs32(ys, q, F[1], k2);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(hh, double(k2[i]), y[i]));
+  M::rhs32(ys, q, F[1], k3);
+#pragma unroll
+  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(h, double(k3[i]), y[i]));
+  M::rhs32(ys, q, F[2], k4);
+  const double h6 = h * (1.0 / 6.0);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    yn[i] = fma(h6, double(fmaf(2.0f, k2[i] + k3[i], k1[i] + k4[i])), y[i]);
 }
 
 // One classical RK4 step of length h from (t, y).
@@ -231,7 +336,7 @@ __device__ __forceinline__ EventCtl event_of(ParamsRef q, int j) {
   return e;
 }
 
-template <class M, int METHOD, int NEV, int NACC>
+template <class M, int METHOD, int PREC, int NEV, int NACC>
 __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   const Control &c = prm.c;
   constexpr int N = M::NS;
@@ -245,6 +350,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   bool active = false;
   double t = 0.0, t1 = 0.0, h = 0.0;
   double y[N], p[P];
+  float pf[PREC == kPrecMixed ? P : 1];  // FP32 copy of the parameters (mixed precision)
   int32_t attempts = 0, n_acc = 0, n_rej = 0, flags = 0, status = kRunning;
   bool window_open = false;
   double accv[AC], acct[AC];
@@ -265,6 +371,8 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   for (int i = 0; i < N; ++i) y[i] = 0.0;
 #pragma unroll
   for (int j = 0; j < P; ++j) p[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < (PREC == kPrecMixed ? P : 1); ++j) pf[j] = 0.0f;
 #pragma unroll
   for (int j = 0; j < EV; ++j) F[j] = 0.0, zone[j] = cnt[j] = wcnt[j] = 0;
 #pragma unroll
@@ -339,6 +447,10 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             for (int i = 0; i < N; ++i) y[i] = a.y[i * ld + s];
 #pragma unroll
             for (int j = 0; j < P; ++j) p[j] = a.p[j * ld + s];
+            if constexpr (PREC == kPrecMixed) {
+#pragma unroll
+              for (int j = 0; j < P; ++j) pf[j] = static_cast<float>(p[j]);
+            }
             attempts = n_acc = n_rej = flags = 0;
             status = kRunning;
             locating = false;
@@ -410,10 +522,17 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 
     // ---- the attempt: one full method step from (t, y) ----
     double yn[N], err[N];
-    if (METHOD == kMethodRK4)
-      rk4_attempt<M>(t, y, p, h_att, yn);
-    else
-      cash_karp_attempt<M>(t, y, p, h_att, yn, err);
+    if constexpr (PREC == kPrecMixed) {
+      if (METHOD == kMethodRK4)
+        rk4_attempt_mixed<M>(t, y, p, pf, h_att, yn);
+      else
+        cash_karp_attempt_mixed<M>(t, y, p, pf, h_att, yn, err);
+    } else {
+      if (METHOD == kMethodRK4)
+        rk4_attempt<M>(t, y, p, h_att, yn);
+      else
+        cash_karp_attempt<M>(t, y, p, h_att, yn, err);
+    }
     ++attempts;
 
     bool commit = false, located = false;
@@ -636,32 +755,38 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   }
 }
 
-// Instantiation table for one model: kernels for both methods and every
-// compiled (event slots, accessory slots) pair.
+// Instantiation table for one model: kernels for both methods, both
+// precisions and every compiled (event slots, accessory slots) pair.
 template <class M>
 struct ModelKernels {
-  template <int METHOD, int NEV, int NACC>
+  template <int METHOD, int PREC, int NEV, int NACC>
   static const void *fn() {
-    return reinterpret_cast<const void *>(&ode_integrate<M, METHOD, NEV, NACC>);
+    return reinterpret_cast<const void *>(&ode_integrate<M, METHOD, PREC, NEV, NACC>);
   }
-  template <int METHOD>
+  template <int METHOD, int PREC>
   static const void *by_slots(int nev, int nacc) {
     switch (nev * 10 + nacc) {
-      case 0: return fn<METHOD, 0, 0>();
-      case 2: return fn<METHOD, 0, 2>();
-      case 4: return fn<METHOD, 0, 4>();
-      case 10: return fn<METHOD, 1, 0>();
-      case 12: return fn<METHOD, 1, 2>();
-      case 14: return fn<METHOD, 1, 4>();
-      case 40: return fn<METHOD, 4, 0>();
-      case 42: return fn<METHOD, 4, 2>();
-      case 44: return fn<METHOD, 4, 4>();
+      case 0: return fn<METHOD, PREC, 0, 0>();
+      case 2: return fn<METHOD, PREC, 0, 2>();
+      case 4: return fn<METHOD, PREC, 0, 4>();
+      case 10: return fn<METHOD, PREC, 1, 0>();
+      case 12: return fn<METHOD, PREC, 1, 2>();
+      case 14: return fn<METHOD, PREC, 1, 4>();
+      case 40: return fn<METHOD, PREC, 4, 0>();
+      case 42: return fn<METHOD, PREC, 4, 2>();
+      case 44: return fn<METHOD, PREC, 4, 4>();
       default: return nullptr;
     }
   }
-  static const void *get(int method, int nev, int nacc) {
-    if (method == kMethodRKCK45) return by_slots<kMethodRKCK45>(nev, nacc);
-    if (method == kMethodRK4) return by_slots<kMethodRK4>(nev, nacc);
+  template <int PREC>
+  static const void *by_method(int method, int nev, int nacc) {
+    if (method == kMethodRKCK45) return by_slots<kMethodRKCK45, PREC>(nev, nacc);
+    if (method == kMethodRK4) return by_slots<kMethodRK4, PREC>(nev, nacc);
+    return nullptr;
+  }
+  static const void *get(int method, int prec, int nev, int nacc) {
+    if (prec == kPrecFP64) return by_method<kPrecFP64>(method, nev, nacc);
+    if (prec == kPrecMixed) return by_method<kPrecMixed>(method, nev, nacc);
     return nullptr;
   }
 };

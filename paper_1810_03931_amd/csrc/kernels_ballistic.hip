@@ -4,8 +4,8 @@
 
 namespace odeens {
 
-const void *kernels_ballistic(int method, int nev, int nacc) {
-  return ModelKernels<Ballistic>::get(method, nev, nacc);
+const void *kernels_ballistic(int method, int prec, int nev, int nacc) {
+  return ModelKernels<Ballistic>::get(method, prec, nev, nacc);
 }
 
 }  // namespace odeens

@@ -4,8 +4,8 @@
 
 namespace odeens {
 
-const void *kernels_duffing(int method, int nev, int nacc) {
-  return ModelKernels<Duffing>::get(method, nev, nacc);
+const void *kernels_duffing(int method, int prec, int nev, int nacc) {
+  return ModelKernels<Duffing>::get(method, prec, nev, nacc);
 }
 
 }  // namespace odeens

@@ -4,8 +4,8 @@
 
 namespace odeens {
 
-const void *kernels_keller_miksis(int method, int nev, int nacc) {
-  return ModelKernels<KellerMiksis>::get(method, nev, nacc);
+const void *kernels_keller_miksis(int method, int prec, int nev, int nacc) {
+  return ModelKernels<KellerMiksis>::get(method, prec, nev, nacc);
 }
 
 }  // namespace odeens

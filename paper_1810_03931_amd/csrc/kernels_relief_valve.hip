@@ -4,8 +4,8 @@
 
 namespace odeens {
 
-const void *kernels_relief_valve(int method, int nev, int nacc) {
-  return ModelKernels<ReliefValve>::get(method, nev, nacc);
+const void *kernels_relief_valve(int method, int prec, int nev, int nacc) {
+  return ModelKernels<ReliefValve>::get(method, prec, nev, nacc);
 }
 
 }  // namespace odeens

@@ -58,6 +58,18 @@ __device__ __forceinline__ void sincos_near(double arg, double base, double sb, 
   }
 }
 
+// Mixed precision: sin/cos of a phase known in FP64, evaluated in FP32.  The
+// phase is turned into revolutions and reduced to [-1/2, 1/2] in FP64 (exact
+// subtraction of the nearest integer), and the hardware sine/cosine, which
+// take revolutions, finish in FP32 (~1e-7 absolute).
+__device__ __forceinline__ float sin_turns(double turns) {
+  return __builtin_amdgcn_sinf(static_cast<float>(turns - rint(turns)));
+}
+__device__ __forceinline__ float cos_turns(double turns) {
+  return __builtin_amdgcn_cosf(static_cast<float>(turns - rint(turns)));
+}
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+
 // Duffing oscillator, paper Sec. 2.1 Eqs. (1)-(2), with linear and cubic
 // stiffness as parameters: p = (k, B, omega, lin, cub),
 //   y1' = y2,  y2' = -lin*y1 - cub*y1^3 - k*y2 + B*cos(omega*t).
@@ -87,6 +99,19 @@ struct Duffing {
     const double spring = fma(p[4] * y1 * y1, y1, fma(p[3], y1, p[0] * y2));
     f[0] = y2;
     f[1] = fma(p[1], F[0], -spring);
+  }
+  template <int S>
+  __device__ __forceinline__ static void forcing32(const double (&ts)[S], const double (&p)[NP],
+                                                   float (&F)[S][NF]) {
+#pragma unroll
+    for (int k = 0; k < S; ++k) F[k][0] = cos_turns(__dmul_rn(p[2], ts[k]) * kInvTwoPi);
+  }
+  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&p)[NP],
+                                               const float (&F)[NF], float (&f)[NS]) {
+    const float y1 = y[0], y2 = y[1];
+    const float spring = fmaf(p[4] * y1 * y1, y1, fmaf(p[3], y1, p[0] * y2));
+    f[0] = y2;
+    f[1] = fmaf(p[1], F[0], -spring);
   }
 };
 
@@ -138,6 +163,38 @@ struct KellerMiksis {
     f[0] = y2;
     f[1] = N / D;
   }
+  template <int S>
+  __device__ __forceinline__ static void forcing32(const double (&ts)[S], const double (&C)[NP],
+                                                   float (&F)[S][NF]) {
+    const double off = C[12] * kInvTwoPi;   // phase offset in revolutions
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const double r2 = fma(C[11], ts[k], off);
+      F[k][0] = sin_turns(ts[k]);           // 2*pi*tau is tau revolutions
+      F[k][1] = cos_turns(ts[k]);
+      F[k][2] = sin_turns(r2);
+      F[k][3] = cos_turns(r2);
+    }
+  }
+  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&C)[NP],
+                                               const float (&F)[NF], float (&f)[NS]) {
+    const float y1 = y[0], y2 = y[1];
+    const float rx = 1.0f / y1;
+    const float gas = __builtin_amdgcn_exp2f(C[10] * __builtin_amdgcn_logf(rx));
+    const float u = fmaf(C[9], y2, 1.0f);
+    const float forcing_p = fmaf(C[5], F[0], C[6] * F[2]);
+    const float forcing_d = fmaf(C[7], F[1], C[8] * F[3]);
+    const float inertia = fmaf(-C[9] * (1.0f / 3.0f), y2, 1.0f) * 1.5f * y2 * y2;
+    float N = fmaf(C[1], y2, C[0]) * gas;
+    N = fmaf(-C[2], u, N);
+    N = fmaf(-fmaf(C[4], y2, C[3]), rx, N);
+    N -= inertia;
+    N = fmaf(-forcing_p, u, N);
+    N = fmaf(-y1, forcing_d, N);
+    const float D = fmaf(-C[9] * y1, y2, y1) + C[4] * C[9];
+    f[0] = y2;
+    f[1] = N / D;
+  }
 };
 
 // Pressure relief valve, paper Sec. 2.3 Eqs. (29)-(31):
@@ -156,6 +213,15 @@ struct ReliefValve {
     f[1] = fma(-p[0], y[1], y[2] - (y[0] + p[1]));
     f[2] = p[2] * fma(-y[0], sqrt(y[2]), p[3]);
   }
+  template <int S>
+  __device__ __forceinline__ static void forcing32(const double (&)[S], const double (&)[NP],
+                                                   float (&)[S][1]) {}
+  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&p)[NP],
+                                               const float (&)[1], float (&f)[NS]) {
+    f[0] = y[1];
+    f[1] = fmaf(-p[0], y[1], y[2] - (y[0] + p[1]));
+    f[2] = p[2] * fmaf(-y[0], sqrtf(y[2]), p[3]);
+  }
 };
 
 // Free flight under gravity (test model): y1' = y2, y2' = -g.
@@ -169,6 +235,14 @@ struct Ballistic {
                                                  double (&)[S][1]) {}
   __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&p)[NP],
                                              const double (&)[1], double (&f)[NS]) {
+    f[0] = y[1];
+    f[1] = -p[0];
+  }
+  template <int S>
+  __device__ __forceinline__ static void forcing32(const double (&)[S], const double (&)[NP],
+                                                   float (&)[S][1]) {}
+  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&p)[NP],
+                                               const float (&)[1], float (&f)[NS]) {
     f[0] = y[1];
     f[1] = -p[0];
   }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "lib", "libode_ensemble.so")
 
 MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4}
 METHOD = {"rkck45": 0, "rk4": 1}
-PRECISION = {"fp64": 0}
+PRECISION = {"fp64": 0, "mixed": 1}
 ACC_KIND = {"max": 1, "min": 2}
 MAX_STATE, MAX_EVENTS, MAX_ACC = 8, 4, 4
 

@@ -223,6 +223,15 @@ def short_horizon(pb: Problem) -> Problem:
     return pb.with_horizon(periods * T, t_record=0.0)
 
 
+def with_tolerance(pb: Problem, tol: float) -> Problem:
+    """The same sweep at relative and absolute tolerance ``tol``."""
+    p = pb.copy()
+    if p.method == "rkck45":
+        p.options["rtol"] = tol
+        p.options["atol"] = tol
+    return p
+
+
 def stratified_sample(n: int, k: int, seed: int = 0) -> np.ndarray:
     """k distinct system indices spread over [0, n): one per stratum."""
     k = min(k, n)

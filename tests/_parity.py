@@ -47,14 +47,14 @@ def run_oracle(pb, threads: int = 0) -> dict:
     return r
 
 
-def run_gpu(pb, *, block_size: int = 0, index=None, ens=None) -> dict:
+def run_gpu(pb, *, block_size: int = 0, index=None, ens=None, precision: str = "fp64") -> dict:
     import torch
     from paper_1810_03931_amd import ensemble as E
     dev = torch.device("cuda", 0)
     td = torch.as_tensor(pb.time_domain, device=dev).contiguous()
     y = torch.as_tensor(pb.state, device=dev).contiguous()
     p = torch.as_tensor(pb.params, device=dev).contiguous()
-    ens = ens or E.Ensemble(pb.model, pb.method, block_size=block_size)
+    ens = ens or E.Ensemble(pb.model, pb.method, precision=precision, block_size=block_size)
     sidx = None if index is None else torch.as_tensor(np.asarray(index, dtype=np.int64), device=dev)
     out = ens.solve(td, y, p, system_index=sidx, **pb.options)
     torch.cuda.synchronize()
