@@ -44,6 +44,7 @@ int oracle_model_dims(int model, int *n_state, int *n_param) {
   case OR_MODEL_KELLER_MIKSIS: ns = 2; np = 13; break;
   case OR_MODEL_RELIEF_VALVE: ns = 3; np = 5; break;
   case OR_MODEL_BALLISTIC: ns = 2; np = 1; break;
+  case OR_MODEL_DUFFING_LYAPUNOV: ns = 4; np = 5; break;
   default: return -1;
   }
   if (n_state) *n_state = ns;
@@ -63,6 +64,26 @@ static void rhs_duffing(double t, const double *y, const double *p, double *f) {
   double y1 = y[0], y2 = y[1];
   f[0] = y2;
   f[1] = -lin * y1 - cub * y1 * y1 * y1 - k * y2 + B * cos(w * t);
+}
+
+/* Duffing oscillator with its linearisation attached in polar coordinates
+ * (paper Sec. 2.1 Eqs. (3)-(6)): the tangent vector (u, v) = r (cos phi,
+ * sin phi) obeys u' = v, v' = g1 u + g2 v with g1 = dF2/dy1 and
+ * g2 = dF2/dy2 at the current point, so that
+ *   r'   = r ((1 + g1) sin(phi) cos(phi) + g2 sin(phi)^2)
+ *   phi' = -sin(phi)^2 + (g1 cos(phi) + g2 sin(phi)) cos(phi).
+ * For y2' = -lin*y1 - cub*y1^3 - k*y2 + B*cos(omega*t):
+ *   g1 = -lin - 3*cub*y1^2,  g2 = -k.
+ * y = (y1, y2, r, phi), p = (k, B, omega, lin, cub).                        */
+static void rhs_duffing_lyapunov(double t, const double *y, const double *p, double *f) {
+  double k = p[0], lin = p[3], cub = p[4];
+  double y1 = y[0], r = y[2], phi = y[3];
+  rhs_duffing(t, y, p, f);
+  double g1 = -lin - 3.0 * cub * y1 * y1;
+  double g2 = -k;
+  double s = sin(phi), c = cos(phi);
+  f[2] = r * ((1.0 + g1) * s * c + g2 * s * s);
+  f[3] = -s * s + (g1 * c + g2 * s) * c;
 }
 
 /* Keller-Miksis equation in the paper's dimensionless form, Sec. 2.2
@@ -110,6 +131,7 @@ int oracle_rhs(int model, double t, const double *y, const double *p, double *f)
   case OR_MODEL_KELLER_MIKSIS: rhs_keller_miksis(t, y, p, f); return 0;
   case OR_MODEL_RELIEF_VALVE: rhs_relief_valve(t, y, p, f); return 0;
   case OR_MODEL_BALLISTIC: rhs_ballistic(t, y, p, f); return 0;
+  case OR_MODEL_DUFFING_LYAPUNOV: rhs_duffing_lyapunov(t, y, p, f); return 0;
   default: return -1;
   }
 }
@@ -263,8 +285,13 @@ typedef struct {
 static void accessories_init(const or_options *o, double t, const double *y, double *accv,
                              double *acct) {
   for (int a = 0; a < o->n_acc; ++a) {
-    accv[a] = y[o->acc[a].component];
-    acct[a] = t;
+    if (o->acc[a].kind == OR_ACC_LOG_RESET) {
+      accv[a] = 0.0; /* sum of logarithms */
+      acct[a] = 0.0; /* number of sections */
+    } else {
+      accv[a] = y[o->acc[a].component];
+      acct[a] = t;
+    }
   }
 }
 
@@ -273,6 +300,7 @@ static void accessories_init(const or_options *o, double t, const double *y, dou
 static void accessories_update(const or_options *o, double t, const double *y, double *accv,
                                double *acct) {
   for (int a = 0; a < o->n_acc; ++a) {
+    if (o->acc[a].kind == OR_ACC_LOG_RESET) continue; /* acts at sections only */
     double v = y[o->acc[a].component];
     if (o->acc[a].kind == OR_ACC_MAX ? (v > accv[a]) : (v < accv[a])) {
       accv[a] = v;
@@ -336,6 +364,22 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
 
   if (!isfinite(t0) || !isfinite(t1)) status = OR_BAD_INPUT;
 
+  /* Poincare sections (paper Sec. 2.1: t_n = n*T).  READING R29: n counts
+   * from the origin of time, not from t0, so a solve split in two visits the
+   * same sections; the next section is the first n*T (rounded product)
+   * strictly after t0, and every section is a forced step boundary. */
+  const double T = o->section_period;
+  long long sec_n = 0;
+  double t_sec = INFINITY;
+  if (status < 0 && T > 0.0) {
+    sec_n = (long long)floor(t0 / T) + 1;
+    t_sec = (double)sec_n * T;
+    while (t_sec <= t0) {
+      sec_n++;
+      t_sec = (double)sec_n * T;
+    }
+  }
+
   /* Accessory initialisation (paper Sec. 6.8) at the start of the window. */
   if (status < 0 && o->t_record <= t0) {
     window_open = 1;
@@ -354,6 +398,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
     /* The next forced boundary: the start of the recording window, then t1
      * (READING R7: steps are clipped so that t lands exactly on it). */
     double t_b = (!window_open && o->t_record < t1) ? o->t_record : t1;
+    if (t_sec < t_b) t_b = t_sec;
 
     double h_try;
     int clipped = 0;
@@ -543,6 +588,25 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
       if (e->stop_after > 0 && count[j] == e->stop_after) status = OR_STOP_EVENT;
     }
 
+    /* Poincare section reached (the step was clipped to it, so t equals the
+     * section time exactly): the Lyapunov accumulators add ln y[c] if the
+     * section lies after the window start, and y[c] restarts from 1 (paper
+     * Sec. 2.1; READING R30: the logarithm of the reset component, averaged
+     * per unit time by the caller as sum / (count * T)). */
+    if (t == t_sec) {
+      for (int a = 0; a < o->n_acc; ++a) {
+        if (o->acc[a].kind != OR_ACC_LOG_RESET) continue;
+        int c = o->acc[a].component;
+        if (window_open && t > o->t_record) {
+          accv[a] = accv[a] + log(y[c]);
+          acct[a] = acct[a] + 1.0;
+        }
+        y[c] = 1.0;
+      }
+      sec_n++;
+      t_sec = (double)sec_n * T;
+    }
+
     /* Event states after the step: a system is in the normal state for event
      * j exactly when it is outside that event's zone; while it stays inside,
      * the accepted steps are counted for the equilibrium stop (paper Sec. 4,
@@ -601,6 +665,7 @@ static int options_ok(const or_options *o, int *n_state) {
         return 0;
   }
   if (o->max_steps <= 0) return 0;
+  if (!(o->section_period >= 0.0) || !isfinite(o->section_period)) return 0;
   if (o->n_events < 0 || o->n_events > OR_MAX_EVENTS) return 0;
   if (o->n_acc < 0 || o->n_acc > OR_MAX_ACC) return 0;
   if (o->record_cap < 0) return 0;
@@ -618,7 +683,10 @@ static int options_ok(const or_options *o, int *n_state) {
   }
   if (n_rec > 1) return 0;
   for (int a = 0; a < o->n_acc; ++a) {
-    if (o->acc[a].kind != OR_ACC_MAX && o->acc[a].kind != OR_ACC_MIN) return 0;
+    if (o->acc[a].kind != OR_ACC_MAX && o->acc[a].kind != OR_ACC_MIN &&
+        o->acc[a].kind != OR_ACC_LOG_RESET)
+      return 0;
+    if (o->acc[a].kind == OR_ACC_LOG_RESET && !(o->section_period > 0.0)) return 0;
     if (o->acc[a].component < 0 || o->acc[a].component >= ns) return 0;
   }
   *n_state = ns;

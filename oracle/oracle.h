@@ -33,14 +33,20 @@ enum {
   OR_MODEL_DUFFING = 1,          /* 2 states, params (k, B, omega, lin, cub)   */
   OR_MODEL_KELLER_MIKSIS = 2,    /* 2 states, params C0..C12                   */
   OR_MODEL_RELIEF_VALVE = 3,     /* 3 states, params (kappa, delta, beta, q, r) */
-  OR_MODEL_BALLISTIC = 4         /* 2 states, params (g)                        */
+  OR_MODEL_BALLISTIC = 4,        /* 2 states, params (g)                        */
+  OR_MODEL_DUFFING_LYAPUNOV = 5  /* 4 states (y1, y2, r, phi), Duffing's params */
 };
 
 /* Integration schemes (paper Sec. 3). */
 enum { OR_RKCK45 = 0, OR_RK4 = 1 };
 
-/* Accessory kinds (paper Sec. 5): running extreme of a component + its time. */
-enum { OR_ACC_MAX = 1, OR_ACC_MIN = 2 };
+/* Accessory kinds (paper Sec. 5): running extreme of a component + its time;
+ * OR_ACC_LOG_RESET is the Lyapunov-exponent accumulator of paper Sec. 2.1:
+ * at every Poincare section t_n the component is reset to 1 after its
+ * logarithm has been added to the first slot; the second slot counts the
+ * sections added.  Both start at 0 when the recording window opens, and only
+ * sections after the window start are added (the reset happens at all). */
+enum { OR_ACC_MAX = 1, OR_ACC_MIN = 2, OR_ACC_LOG_RESET = 3 };
 
 /* Per-system outcome. */
 enum {
@@ -81,6 +87,8 @@ typedef struct {
   double grow;      /* largest step growth factor after an accepted step   */
   double shrink;    /* smallest step factor after a rejected step          */
   double t_record;  /* start of the recording window (absolute time)       */
+  double section_period; /* > 0: Poincare sections at t_n = n*T (absolute,
+                          * n integer) are forced step boundaries; 0: none */
   int max_equilibrium_steps; /* 0 disables the equilibrium stop            */
   long long max_steps;       /* attempt budget per system                  */
   int n_events;

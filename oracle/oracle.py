@@ -13,10 +13,12 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4}
+MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4,
+         "duffing_lyapunov": 5}
 METHOD = {"rkck45": 0, "rk4": 1}
-ACC = {"max": 1, "min": 2}
-DIMS = {"duffing": (2, 5), "keller_miksis": (2, 13), "relief_valve": (3, 5), "ballistic": (2, 1)}
+ACC = {"max": 1, "min": 2, "log_reset": 3}
+DIMS = {"duffing": (2, 5), "keller_miksis": (2, 13), "relief_valve": (3, 5), "ballistic": (2, 1),
+        "duffing_lyapunov": (4, 5)}
 
 DONE, STOP_EVENT, STOP_EQUILIBRIUM, FAIL_NAN, MAX_STEPS, BAD_INPUT = range(6)
 FLAG_SECANT_CAP = 0x100
@@ -41,7 +43,7 @@ class _Options(C.Structure):
         ("rtol", C.c_double * 8), ("atol", C.c_double * 8),
         ("h0", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
         ("grow", C.c_double), ("shrink", C.c_double), ("t_record", C.c_double),
-        ("max_equilibrium_steps", C.c_int), ("max_steps", C.c_longlong),
+        ("section_period", C.c_double), ("max_equilibrium_steps", C.c_int), ("max_steps", C.c_longlong),
         ("n_events", C.c_int), ("n_acc", C.c_int), ("record_cap", C.c_int),
         ("ev", _Event * 4), ("acc", _Acc * 4),
     ]
@@ -109,7 +111,8 @@ def step(model, method, t, y, p, h):
 
 
 def make_options(model, method, *, h0, rtol=1e-10, atol=1e-10, h_min=1e-12, h_max=1e6,
-                 grow=5.0, shrink=0.1, t_record=-np.inf, max_equilibrium_steps=0,
+                 grow=5.0, shrink=0.1, t_record=-np.inf, section_period=0.0,
+                 max_equilibrium_steps=0,
                  max_steps=10**9, events=(), accessories=(), record_cap=0):
     o = _Options()
     o.model, o.method = MODEL[model], METHOD[method]
@@ -119,7 +122,7 @@ def make_options(model, method, *, h0, rtol=1e-10, atol=1e-10, h_min=1e-12, h_ma
     for i in range(ns):
         o.rtol[i], o.atol[i] = float(rt[i]), float(at[i])
     o.h0, o.h_min, o.h_max, o.grow, o.shrink = h0, h_min, h_max, grow, shrink
-    o.t_record = t_record
+    o.t_record, o.section_period = t_record, section_period
     o.max_equilibrium_steps, o.max_steps = max_equilibrium_steps, max_steps
     o.n_events, o.n_acc, o.record_cap = len(events), len(accessories), record_cap
     for j, e in enumerate(events):
