@@ -24,6 +24,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1810_03931_amd import inputs as I  # noqa: E402  (input generators only)
+
 METRIC = "system-steps/s + % FP64 VALU peak (RKCK45 sweep); p50/p99 sweep latency"
 FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
 
@@ -43,6 +45,7 @@ FLOPS_ESTIMATE = {
     ("duffing", "rkck45"): 191 + 7 * 40,
     ("keller_miksis", "rkck45"): 359 + 19 * 40,
     ("relief_valve", "rkck45"): 237 + 7 * 40,
+    ("duffing_lyapunov", "rkck45"): 875,
 }
 
 
@@ -52,8 +55,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="duffing_rkck45",
-                    choices=["duffing_rk4", "duffing_rkck45", "keller_miksis", "relief_valve"])
+                    choices=sorted(I.CONFIGS))
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="cap on resident workgroups per compute unit (0: all that fit)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the launch configuration (untimed) before the warmup")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=0.0,
                     help="override rtol = atol of the sweep (0: the sweep's own)")
@@ -163,7 +170,8 @@ def main():
         pb.params[:] = pb.params[:, args.uniform:args.uniform + 1]
         pb.state[:] = pb.state[:, args.uniform:args.uniform + 1]
         pb.time_domain[:] = pb.time_domain[:, args.uniform:args.uniform + 1]
-    ens = E.Ensemble(pb.model, pb.method, precision=args.precision, block_size=args.block_size)
+    ens = E.Ensemble(pb.model, pb.method, precision=args.precision, block_size=args.block_size,
+                     blocks_per_cu=args.blocks_per_cu)
     td0 = torch.as_tensor(pb.time_domain, device=dev).contiguous()
     y0 = torch.as_tensor(pb.state, device=dev).contiguous()
     p = torch.as_tensor(pb.params, device=dev).contiguous()
@@ -173,6 +181,10 @@ def main():
     out = ens.outputs(pb.n, n_accessories=len(pb.options.get("accessories", [])),
                       n_events=len(ev), record_cap=cap, device=dev)
     stream = torch.cuda.current_stream(dev)
+    tuned = None
+    if args.tune:
+        tuned = ens.tune(td0, y0, p, probe_fraction=0.25, stream=stream, **pb.options)
+        print(f"tuned launch configuration: {tuned}", file=sys.stderr, flush=True)
 
     def step():
         td.copy_(td0)
@@ -220,11 +232,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32 stages / f64 state",
         "data": "synthetic (seeded parameter sweep)",
-        "config": {"workload": pb.name + ("/uniform" if args.uniform >= 0 else ""), "systems": pb.n, "model": pb.model, "method": pb.method,
+        "config": {"workload": pb.name + ("/uniform" if args.uniform >= 0 else ""),
+                   "systems": pb.n, "equation": pb.model, "method": pb.method,
                    "horizon": float(pb.time_domain[1, 0]), "t_record": pb.options.get("t_record"),
                    "rtol": pb.options.get("rtol"), "precision": args.precision,
-                   "block_size": info["block_size"],
-                   "resident_systems": info["resident_systems"]},
+                   "block_size": info["block_size"], "blocks_per_cu": info["blocks_per_cu"],
+                   "resident_systems": info["resident_systems"], "tuned": tuned is not None},
         "attempted_steps_per_s": attempts / (ms_per_step / 1e3),
         "reject_frac": float(counts[1] / attempts), "location_frac": float(counts[2] / attempts),
         "status_counts": status.tolist(),

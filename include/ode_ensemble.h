@@ -53,12 +53,20 @@ enum ode_error {
  *                  Sec. 2.2 (time is tau, one period of the first forcing).
  *   RELIEF_VALVE   3 states, 5 params (kappa, delta, beta, q, r), Sec. 2.3;
  *                  r is available to event actions through action_param.
- *   BALLISTIC      2 states, 1 param (g): y1' = y2, y2' = -g (test model). */
+ *   BALLISTIC      2 states, 1 param (g): y1' = y2, y2' = -g (test model).
+ *   DUFFING_LYAPUNOV  4 states (y1, y2, r, phi), the DUFFING params: the
+ *                  Duffing system with its linearisation attached in polar
+ *                  coordinates (Sec. 2.1 Eqs. (3)-(6)); r and phi are the
+ *                  length and angle of a tangent vector, with
+ *                  g1 = -lin - 3*cub*y1^2 and g2 = -k.  Combined with
+ *                  section_period and an ODE_ACC_LOG_RESET accessory on r it
+ *                  gives the largest Lyapunov exponent. */
 enum ode_model {
   ODE_MODEL_DUFFING = 1,
   ODE_MODEL_KELLER_MIKSIS = 2,
   ODE_MODEL_RELIEF_VALVE = 3,
-  ODE_MODEL_BALLISTIC = 4
+  ODE_MODEL_BALLISTIC = 4,
+  ODE_MODEL_DUFFING_LYAPUNOV = 5
 };
 
 /* Integration schemes (paper Sec. 3 and Sec. 6.4). */
@@ -74,11 +82,18 @@ enum ode_method { ODE_RKCK45 = 0, ODE_RK4 = 1 };
  *                    tolerances of about 1e-7 and looser. */
 enum ode_precision { ODE_FP64 = 0, ODE_FP32_STAGES = 1 };
 
-/* Accessory kinds (paper Sec. 5 and Sec. 6.7): a running maximum or minimum
- * of one state component over the recording window, with the time at which
- * it was first reached.  Accessory a occupies rows 2a (value) and 2a+1
- * (time) of the accessories array. */
-enum ode_accessory_kind { ODE_ACC_MAX = 1, ODE_ACC_MIN = 2 };
+/* Accessory kinds (paper Sec. 5 and Sec. 6.7).  Accessory a occupies rows 2a
+ * and 2a+1 of the accessories array.
+ *   ODE_ACC_MAX / ODE_ACC_MIN  running maximum / minimum of one state
+ *       component over the recording window (row 2a) and the time at which it
+ *       was first reached (row 2a+1).
+ *   ODE_ACC_LOG_RESET  the Lyapunov accumulator of Sec. 2.1: at every
+ *       Poincare section (see section_period) the component is reset to 1,
+ *       after ln of its value has been added to row 2a when the section lies
+ *       after t_record; row 2a+1 counts the sections added.  The largest
+ *       Lyapunov exponent is row 2a / (row 2a+1 * section_period).  Requires
+ *       section_period > 0. */
+enum ode_accessory_kind { ODE_ACC_MAX = 1, ODE_ACC_MIN = 2, ODE_ACC_LOG_RESET = 3 };
 
 /* Per-system status (low byte) and flags. */
 enum ode_lane_status {
@@ -120,6 +135,9 @@ typedef struct {
   int32_t precision;  /* ode_precision                                      */
   int32_t block_size; /* threads per workgroup, multiple of 64 in [64, 256];
                          0 selects the library default                      */
+  int32_t blocks_per_cu; /* >= 0: at most this many resident workgroups per
+                         compute unit (fewer resident lanes, each taking more
+                         systems from the work queue); 0: as many as fit    */
 } ode_ensemble_desc;
 
 /* One integration call (paper Sec. 6.4 Solve; Sec. 6.5 ODE properties;
@@ -148,6 +166,11 @@ typedef struct {
   const int64_t *system_index;/* [n_systems] systems to integrate (paper
                                  Sec. 6.3 RandomSet); NULL: 0..n_systems-1.
                                  Entries outside [0, ld) are skipped        */
+  const double *record_start; /* [ld] per-system start of the recording
+                                 window, replacing t_record (so requests with
+                                 different windows can share one launch);
+                                 NaN: the window never opens; NULL: t_record
+                                 for every system                          */
   double rtol[ODE_MAX_STATE]; /* per component, >= 0, rtol+atol > 0 (RKCK45) */
   double atol[ODE_MAX_STATE];
   double h0;                  /* initial step (RKCK45) or fixed step (RK4), > 0 */
@@ -160,6 +183,11 @@ typedef struct {
                                  time); accessories are initialised from the
                                  state there (Sec. 6.8) and event counts and
                                  records only cover t >= t_record            */
+  double section_period;      /* T >= 0, finite.  T > 0: the Poincare sections
+                                 t_n = n*T (n integer, counted from time 0)
+                                 are forced step boundaries, where
+                                 ODE_ACC_LOG_RESET accessories act (Sec. 2.1).
+                                 0: no sections                              */
   int64_t max_steps;          /* attempt budget per system, 1..ODE_MAX_STEPS_LIMIT */
   int32_t max_equilibrium_steps; /* >= 0; 0 disables the equilibrium stop   */
   int32_t n_events;           /* 0..ODE_MAX_EVENTS                           */
@@ -206,11 +234,62 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out);
  * the same time; separate handles may run concurrently. */
 int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *args, void *hip_stream);
 
+/* Repeated horizons, captured once as a HIP graph.  This is the paper's
+ * Sec. 7 workflow: a sweep advanced one excitation period per solve call,
+ * each end point starting the next call, with the points of the last calls
+ * kept.  The call is equivalent to the host loop
+ *     for k = 0 .. n_segments-1:
+ *       time_domain[1][s] = time_domain[0][s] + segment    (every system s)
+ *       ode_ensemble_solve(e, args, hip_stream)
+ *       if k >= first_snapshot: copy rows of system s into snapshot
+ *                               k - first_snapshot
+ * and its results are bit-identical to it.
+ * A snapshot is [n_state + 2*n_accessories][ld]: the state after that
+ * segment, then the accessories of that segment.  `snapshots` (device) holds
+ * (n_segments - first_snapshot) of them, back to back, and is NULL iff
+ * first_snapshot == n_segments.
+ * The n_segments x 3 kernel launches are recorded once into a HIP graph on a
+ * stream private to the handle.  The graph is kept on the handle and
+ * relaunched while the arguments (pointers and values) stay the same.  It
+ * contains kernel nodes only.  Each call enqueues one graph launch on
+ * hip_stream and returns without waiting.
+ * Requires n_segments >= 1, 0 <= first_snapshot <= n_segments and a finite
+ * segment > 0; args as for ode_ensemble_solve (its t1 row is overwritten).
+ * Errors: ODE_EINVAL, ODE_EHIP, ODE_ENOMEM. */
+int ode_ensemble_solve_segments(ode_ensemble *e, const ode_solve_args *args,
+                                int32_t n_segments, double segment, int32_t first_snapshot,
+                                double *snapshots, void *hip_stream);
+
+/* Result of ode_ensemble_tune. */
+typedef struct {
+  int32_t block_size;    /* chosen threads per workgroup                    */
+  int32_t blocks_per_cu; /* chosen cap on resident workgroups per CU (0: none) */
+  int32_t candidates;    /* launch configurations timed                     */
+  int32_t reserved;
+  double best_ms;        /* probe time of the chosen configuration          */
+  double default_ms;     /* probe time of the handle's configuration before */
+} ode_tune_result;
+
+/* Autotune the handle's launch configuration for problems like `args` (the
+ * paper tunes threads per block by hand, Sec. 7.1 tables; here the library
+ * measures).  Every candidate (block sizes 64, 128, 256; all resident
+ * workgroups that fit, or half of them) integrates the problem of `args`
+ * over the first probe_fraction of each system's time domain, on private
+ * copies of every array the solve writes, and is timed with HIP events on
+ * hip_stream; the fastest becomes the handle's configuration.  The caller's
+ * arrays are only read.  Synchronous: returns after the probes finished.
+ * Allocates and frees device memory for the copies (about the size of the
+ * caller's arrays).  0 < probe_fraction <= 1.  Errors: ODE_EINVAL,
+ * ODE_ENOMEM, ODE_EHIP. */
+int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *args, double probe_fraction,
+                      void *hip_stream, ode_tune_result *result);
+
 /* Launch facts for the handle.  Errors: ODE_EINVAL for NULL arguments. */
 int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info);
 
-/* Release the handle and its device memory.  NULL is ignored.  The caller
- * must have synchronised every stream the handle was used on. */
+/* Release the handle, its device memory, its private stream and any cached
+ * graph.  NULL is ignored.  The caller must have synchronised every stream
+ * the handle was used on. */
 void ode_ensemble_destroy(ode_ensemble *e);
 
 /* Description of the last error on the calling thread ("" if none). */

@@ -321,6 +321,8 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
 
   double t0 = time_domain[s], t1 = time_domain[ld + s];
   double t = t0;
+  /* start of this system's recording window */
+  const double t_rec = o->record_start ? o->record_start[s] : o->t_record;
   double y[OR_MAX_STATE];
   for (int i = 0; i < n; ++i) y[i] = state[(long long)i * ld + s];
 
@@ -381,7 +383,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
   }
 
   /* Accessory initialisation (paper Sec. 6.8) at the start of the window. */
-  if (status < 0 && o->t_record <= t0) {
+  if (status < 0 && t_rec <= t0) {
     window_open = 1;
     accessories_init(o, t, y, accv, acct);
   }
@@ -397,7 +399,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
     }
     /* The next forced boundary: the start of the recording window, then t1
      * (READING R7: steps are clipped so that t lands exactly on it). */
-    double t_b = (!window_open && o->t_record < t1) ? o->t_record : t1;
+    double t_b = (!window_open && t_rec < t1) ? t_rec : t1;
     if (t_sec < t_b) t_b = t_sec;
 
     double h_try;
@@ -553,7 +555,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
      * inside the recording window; the window opens at the forced boundary
      * t_record where the accessories are initialised from the state. */
     if (!window_open) {
-      if (t >= o->t_record) {
+      if (t >= t_rec) {
         window_open = 1;
         accessories_init(o, t, y, accv, acct);
       }
@@ -597,7 +599,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
       for (int a = 0; a < o->n_acc; ++a) {
         if (o->acc[a].kind != OR_ACC_LOG_RESET) continue;
         int c = o->acc[a].component;
-        if (window_open && t > o->t_record) {
+        if (window_open && t > t_rec) {
           accv[a] = accv[a] + log(y[c]);
           acct[a] = acct[a] + 1.0;
         }

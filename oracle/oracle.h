@@ -89,6 +89,8 @@ typedef struct {
   double t_record;  /* start of the recording window (absolute time)       */
   double section_period; /* > 0: Poincare sections at t_n = n*T (absolute,
                           * n integer) are forced step boundaries; 0: none */
+  const double *record_start; /* [ld] per-system window start replacing
+                               * t_record; NULL: t_record for every system */
   int max_equilibrium_steps; /* 0 disables the equilibrium stop            */
   long long max_steps;       /* attempt budget per system                  */
   int n_events;

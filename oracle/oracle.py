@@ -43,7 +43,8 @@ class _Options(C.Structure):
         ("rtol", C.c_double * 8), ("atol", C.c_double * 8),
         ("h0", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
         ("grow", C.c_double), ("shrink", C.c_double), ("t_record", C.c_double),
-        ("section_period", C.c_double), ("max_equilibrium_steps", C.c_int), ("max_steps", C.c_longlong),
+        ("section_period", C.c_double), ("record_start", C.POINTER(C.c_double)),
+        ("max_equilibrium_steps", C.c_int), ("max_steps", C.c_longlong),
         ("n_events", C.c_int), ("n_acc", C.c_int), ("record_cap", C.c_int),
         ("ev", _Event * 4), ("acc", _Acc * 4),
     ]
@@ -143,7 +144,7 @@ def make_options(model, method, *, h0, rtol=1e-10, atol=1e-10, h_min=1e-12, h_ma
 
 
 def solve(model, method, time_domain, state, params, *, next_h=None, index=None, threads=0,
-          **opts):
+          record_start=None, **opts):
     """Integrate every system (or those in ``index``) in place.
 
     ``time_domain`` [2, ld], ``state`` [n_state, ld] and ``params``
@@ -152,6 +153,10 @@ def solve(model, method, time_domain, state, params, *, next_h=None, index=None,
     Returns a dict with status, counts, acc, event_counts, event_records.
     """
     o = make_options(model, method, **opts)
+    if record_start is not None:
+        record_start = np.ascontiguousarray(record_start, dtype=np.float64)
+        assert record_start.shape == (time_domain.shape[1],)
+        o.record_start = _ptr(record_start, C.c_double)
     td = np.ascontiguousarray(time_domain, dtype=np.float64)
     st = np.ascontiguousarray(state, dtype=np.float64)
     pr = np.ascontiguousarray(params, dtype=np.float64)

@@ -18,6 +18,7 @@ const void *kernels_duffing(int method, int prec, int nev, int nacc);
 const void *kernels_keller_miksis(int method, int prec, int nev, int nacc);
 const void *kernels_relief_valve(int method, int prec, int nev, int nacc);
 const void *kernels_ballistic(int method, int prec, int nev, int nacc);
+const void *kernels_duffing_lyapunov(int method, int prec, int nev, int nacc);
 
 const void *integrator_kernel(int model, int method, int prec, int nev, int nacc) {
   switch (model) {
@@ -25,6 +26,7 @@ const void *integrator_kernel(int model, int method, int prec, int nev, int nacc
     case ODE_MODEL_KELLER_MIKSIS: return kernels_keller_miksis(method, prec, nev, nacc);
     case ODE_MODEL_RELIEF_VALVE: return kernels_relief_valve(method, prec, nev, nacc);
     case ODE_MODEL_BALLISTIC: return kernels_ballistic(method, prec, nev, nacc);
+    case ODE_MODEL_DUFFING_LYAPUNOV: return kernels_duffing_lyapunov(method, prec, nev, nacc);
     default: return nullptr;
   }
 }
@@ -66,6 +68,7 @@ bool model_dims(int32_t model, int32_t *ns, int32_t *np) {
     case ODE_MODEL_KELLER_MIKSIS: *ns = 2; *np = 13; return true;
     case ODE_MODEL_RELIEF_VALVE: *ns = 3; *np = 5; return true;
     case ODE_MODEL_BALLISTIC: *ns = 2; *np = 1; return true;
+    case ODE_MODEL_DUFFING_LYAPUNOV: *ns = 4; *np = 5; return true;
     default: return false;
   }
 }
@@ -81,15 +84,49 @@ int combo_index(int nev, int nacc) {
 
 }  // namespace
 
+// Arguments a cached repeated-horizon graph was recorded for.
+struct SegmentsKey {
+  ode_solve_args args;
+  int32_t n_segments, first_snapshot;
+  double segment;
+  double *snapshots;
+};
+
 struct ode_ensemble {
   int32_t model, method, precision, block;
   int32_t n_state, n_param;
   int device;
   int compute_units;
-  int blocks_per_cu[kCombos];  // 0 = not yet queried
+  int cap;                     // resident workgroups per CU at most (0: no cap)
+  int blocks_per_cu[kMaxBlock / 64][kCombos];  // occupancy per block size; 0 = not queried
   int last_blocks_per_cu, last_grid;
   unsigned long long *queue;   // device: [0] next position, [1] finished waves
+  // repeated horizons: private capture stream and the cached graph
+  hipStream_t capture_stream;
+  hipGraphExec_t segments_exec;
+  SegmentsKey segments_key;
 };
+
+namespace {
+
+// Device copies of every array a solve writes, for the autotuning probes.
+struct ProbeArrays {
+  double *td = nullptr, *y = nullptr, *acc = nullptr, *next_h = nullptr, *rec = nullptr;
+  int32_t *status = nullptr, *evc = nullptr;
+  int64_t *counts = nullptr;
+  ~ProbeArrays() {
+    for (void *p : {(void *)td, (void *)y, (void *)acc, (void *)next_h, (void *)rec,
+                    (void *)status, (void *)evc, (void *)counts})
+      if (p) (void)hipFree(p);
+  }
+};
+
+template <class T>
+hipError_t alloc(T **p, int64_t count) {
+  return count > 0 ? hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count) : hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -117,6 +154,7 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out) {
   if (block < 64 || block > kMaxBlock || block % 64 != 0)
     return fail(ODE_EINVAL, "block_size %d must be a multiple of 64 in [64, %d]",
                 desc->block_size, kMaxBlock);
+  if (desc->blocks_per_cu < 0) return fail(ODE_EINVAL, "blocks_per_cu must be >= 0");
 
   int dev = 0;
   hipError_t err = hipGetDevice(&dev);
@@ -131,6 +169,7 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out) {
   e->method = desc->method;
   e->precision = desc->precision;
   e->block = block;
+  e->cap = desc->blocks_per_cu;
   e->n_state = ns;
   e->n_param = np;
   e->device = dev;
@@ -155,21 +194,25 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out) {
 
 void ode_ensemble_destroy(ode_ensemble *e) {
   if (!e) return;
+  if (e->segments_exec) (void)hipGraphExecDestroy(e->segments_exec);
+  if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
   if (e->queue) (void)hipFree(e->queue);
   std::free(e);
 }
 
-static int query_blocks(ode_ensemble *e, int nev, int nacc, int *out) {
-  int &slot = e->blocks_per_cu[combo_index(nev, nacc)];
+// Resident workgroups per CU for a block size and slot combination, after
+// the handle's cap.
+static int query_blocks(ode_ensemble *e, int block, int nev, int nacc, int *out) {
+  int &slot = e->blocks_per_cu[block / 64 - 1][combo_index(nev, nacc)];
   if (slot == 0) {
     const void *fn = integrator_kernel(e->model, e->method, e->precision, nev, nacc);
     if (!fn) return fail(ODE_ENOTSUP, "no kernel for this model/method");
     int nb = 0;
-    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, e->block, 0);
+    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0);
     if (err != hipSuccess) return hip_fail(err, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
     slot = nb > 0 ? nb : 1;
   }
-  *out = slot;
+  *out = (e->cap > 0 && e->cap < slot) ? e->cap : slot;
   return ODE_OK;
 }
 
@@ -178,7 +221,7 @@ int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info) {
   auto *m = const_cast<ode_ensemble *>(e);
   int bpc = e->last_blocks_per_cu;
   if (bpc == 0) {
-    int rc = query_blocks(m, 0, 0, &bpc);
+    int rc = query_blocks(m, e->block, 0, 0, &bpc);
     if (rc != ODE_OK) return rc;
   }
   info->block_size = e->block;
@@ -219,6 +262,8 @@ static int validate(const ode_ensemble *e, const ode_solve_args *a) {
     return fail(ODE_EINVAL, "max_steps must be in [1, %lld]", (long long)ODE_MAX_STEPS_LIMIT);
   if (a->max_equilibrium_steps < 0) return fail(ODE_EINVAL, "max_equilibrium_steps < 0");
   if (std::isnan(a->t_record)) return fail(ODE_EINVAL, "t_record is NaN");
+  if (!(a->section_period >= 0.0) || !std::isfinite(a->section_period))
+    return fail(ODE_EINVAL, "section_period must be finite and >= 0");
   if (e->method == ODE_RKCK45) {
     if (!finite_pos(a->h_min)) return fail(ODE_EINVAL, "h_min must be finite and > 0");
     if (!(a->h_max >= a->h_min)) return fail(ODE_EINVAL, "h_max < h_min");
@@ -252,21 +297,19 @@ static int validate(const ode_ensemble *e, const ode_solve_args *a) {
   if (recording > 1) return fail(ODE_EINVAL, "at most one event may record");
   for (int k = 0; k < a->n_accessories; ++k) {
     const ode_accessory_spec &s = a->accessory_specs[k];
-    if (s.kind != ODE_ACC_MAX && s.kind != ODE_ACC_MIN)
+    if (s.kind != ODE_ACC_MAX && s.kind != ODE_ACC_MIN && s.kind != ODE_ACC_LOG_RESET)
       return fail(ODE_EINVAL, "accessory %d: unknown kind %d", k, s.kind);
+    if (s.kind == ODE_ACC_LOG_RESET && !(a->section_period > 0.0))
+      return fail(ODE_EINVAL, "accessory %d: ODE_ACC_LOG_RESET needs section_period > 0", k);
     if (s.component < 0 || s.component >= ns)
       return fail(ODE_EINVAL, "accessory %d: component out of range", k);
   }
   return ODE_OK;
 }
 
-int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_stream) {
-  if (!e || !a) return fail(ODE_EINVAL, "NULL handle or arguments");
-  int rc = validate(e, a);
-  if (rc != ODE_OK) return rc;
-  if (a->n_systems == 0) return ODE_OK;
-
-  Params prm;
+// Launch parameters of one solve (arguments already validated).
+static int prepare_launch(ode_ensemble *e, const ode_solve_args *a, Params &prm, int &nev,
+                          int &nacc, int &grid) {
   std::memset(&prm, 0, sizeof prm);
   Control &c = prm.c;
   for (int i = 0; i < ODE_MAX_STATE; ++i) {
@@ -279,6 +322,7 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   c.grow = a->grow;
   c.shrink = a->shrink;
   c.t_record = a->t_record;
+  c.section_period = a->section_period;
   c.max_steps = static_cast<int32_t>(a->max_steps);
   c.max_eq = a->max_equilibrium_steps;
   c.n_events = a->n_events;
@@ -292,14 +336,14 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   for (int k = 0; k < a->n_accessories; ++k)
     c.acc[k] = AccCtl{a->accessory_specs[k].kind, a->accessory_specs[k].component};
 
-  const int nev = event_slots(a->n_events);
-  const int nacc = acc_slots(a->n_accessories);
+  nev = event_slots(a->n_events);
+  nacc = acc_slots(a->n_accessories);
   int bpc = 0;
-  rc = query_blocks(e, nev, nacc, &bpc);
+  int rc = query_blocks(e, e->block, nev, nacc, &bpc);
   if (rc != ODE_OK) return rc;
   const int64_t max_grid = (int64_t)bpc * e->compute_units;
   const int64_t need = (a->n_systems + e->block - 1) / e->block;
-  const int grid = static_cast<int>(need < max_grid ? need : max_grid);
+  grid = static_cast<int>(need < max_grid ? need : max_grid);
 
   Arrays &arr = prm.a;
   arr.td = a->time_domain;
@@ -312,16 +356,228 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   arr.evc = a->event_counts;
   arr.rec = a->event_records;
   arr.index = a->system_index;
+  arr.t_rec = a->record_start;
   arr.n = a->n_systems;
   arr.ld = a->ld;
   arr.queue = e->queue;
   arr.total_waves = static_cast<uint32_t>(grid) * static_cast<uint32_t>(e->block / 64);
+  e->last_blocks_per_cu = bpc;
+  e->last_grid = grid;
+  return ODE_OK;
+}
 
+int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_stream) {
+  if (!e || !a) return fail(ODE_EINVAL, "NULL handle or arguments");
+  int rc = validate(e, a);
+  if (rc != ODE_OK) return rc;
+  if (a->n_systems == 0) return ODE_OK;
+  Params prm;
+  int nev = 0, nacc = 0, grid = 0;
+  rc = prepare_launch(e, a, prm, nev, nacc, grid);
+  if (rc != ODE_OK) return rc;
   hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid,
                                      e->block, static_cast<hipStream_t>(hip_stream));
   if (err != hipSuccess) return hip_fail(err, "integrator launch");
-  e->last_blocks_per_cu = bpc;
-  e->last_grid = grid;
+  return ODE_OK;
+}
+
+// Records the whole repeated-horizon sequence on the handle's private stream.
+static int record_segments(ode_ensemble *e, const ode_solve_args *a, int32_t n_segments,
+                           double segment, int32_t first_snapshot, double *snapshots,
+                           hipGraphExec_t *out) {
+  Params prm;
+  int nev = 0, nacc = 0, grid = 0;
+  int rc = prepare_launch(e, a, prm, nev, nacc, grid);
+  if (rc != ODE_OK) return rc;
+  const int rows = e->n_state + 2 * a->n_accessories;
+  hipStream_t cs = e->capture_stream;
+  hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (err != hipSuccess) return hip_fail(err, "hipStreamBeginCapture");
+  hipError_t first = hipSuccess;
+  for (int32_t k = 0; k < n_segments && first == hipSuccess; ++k) {
+    first = launch_set_horizon(a->time_domain, a->ld, a->n_systems, a->system_index, segment, cs);
+    if (first == hipSuccess)
+      first = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid, e->block,
+                                cs);
+    if (first == hipSuccess && k >= first_snapshot)
+      first = launch_snapshot(a->state, e->n_state, a->accessories, 2 * a->n_accessories, a->ld,
+                              a->n_systems, a->system_index,
+                              snapshots + (int64_t)(k - first_snapshot) * rows * a->ld, cs);
+  }
+  hipGraph_t graph = nullptr;
+  err = hipStreamEndCapture(cs, &graph);
+  if (first != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(first, "recording the segment launches");
+  }
+  if (err != hipSuccess) return hip_fail(err, "hipStreamEndCapture");
+  err = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (err != hipSuccess) return hip_fail(err, "hipGraphInstantiate");
+  return ODE_OK;
+}
+
+int ode_ensemble_solve_segments(ode_ensemble *e, const ode_solve_args *a, int32_t n_segments,
+                                double segment, int32_t first_snapshot, double *snapshots,
+                                void *hip_stream) {
+  if (!e || !a) return fail(ODE_EINVAL, "NULL handle or arguments");
+  int rc = validate(e, a);
+  if (rc != ODE_OK) return rc;
+  if (n_segments < 1) return fail(ODE_EINVAL, "n_segments must be >= 1");
+  if (!finite_pos(segment)) return fail(ODE_EINVAL, "segment must be finite and > 0");
+  if (first_snapshot < 0 || first_snapshot > n_segments)
+    return fail(ODE_EINVAL, "first_snapshot must be in [0, n_segments]");
+  if (a->n_systems > 0 && (first_snapshot < n_segments) != (snapshots != nullptr))
+    return fail(ODE_EINVAL, "snapshots must be given exactly when first_snapshot < n_segments");
+  if (a->n_systems > (int64_t(1) << 38)) return fail(ODE_EINVAL, "n_systems too large");
+  if (a->n_systems == 0) return ODE_OK;
+
+  SegmentsKey key;
+  std::memset(&key, 0, sizeof key);
+  key.args = *a;
+  key.n_segments = n_segments;
+  key.first_snapshot = first_snapshot;
+  key.segment = segment;
+  key.snapshots = snapshots;
+  // the event and accessory arrays beyond the counts in use do not matter
+  for (int j = a->n_events; j < ODE_MAX_EVENTS; ++j) std::memset(&key.args.events[j], 0, sizeof(ode_event_spec));
+  for (int k = a->n_accessories; k < ODE_MAX_ACCESSORIES; ++k)
+    std::memset(&key.args.accessory_specs[k], 0, sizeof(ode_accessory_spec));
+  if (!e->capture_stream) {
+    hipError_t err = hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+      e->capture_stream = nullptr;
+      return hip_fail(err, "hipStreamCreateWithFlags");
+    }
+  }
+  if (!e->segments_exec || std::memcmp(&key, &e->segments_key, sizeof key) != 0) {
+    if (e->segments_exec) {
+      (void)hipGraphExecDestroy(e->segments_exec);
+      e->segments_exec = nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    rc = record_segments(e, a, n_segments, segment, first_snapshot, snapshots, &exec);
+    if (rc != ODE_OK) return rc;
+    e->segments_exec = exec;
+    e->segments_key = key;
+  }
+  hipError_t err = hipGraphLaunch(e->segments_exec, static_cast<hipStream_t>(hip_stream));
+  if (err != hipSuccess) return hip_fail(err, "hipGraphLaunch");
+  return ODE_OK;
+}
+
+int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *a, double probe_fraction,
+                      void *hip_stream, ode_tune_result *result) {
+  if (!e || !a || !result) return fail(ODE_EINVAL, "NULL handle, arguments or result");
+  int rc = validate(e, a);
+  if (rc != ODE_OK) return rc;
+  if (!(probe_fraction > 0.0 && probe_fraction <= 1.0))
+    return fail(ODE_EINVAL, "probe_fraction must be in (0, 1]");
+  std::memset(result, 0, sizeof *result);
+  result->block_size = e->block;
+  result->blocks_per_cu = e->cap;
+  if (a->n_systems == 0) return ODE_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t ld = a->ld;
+
+  ProbeArrays c;
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t x) { if (err == hipSuccess) err = x; };
+  chk(alloc(&c.td, 2 * ld));
+  chk(alloc(&c.y, (int64_t)e->n_state * ld));
+  chk(alloc(&c.status, ld));
+  chk(alloc(&c.counts, 3 * ld));
+  if (a->n_accessories) chk(alloc(&c.acc, 2 * (int64_t)a->n_accessories * ld));
+  if (a->next_h) chk(alloc(&c.next_h, ld));
+  if (a->n_events) chk(alloc(&c.evc, (int64_t)a->n_events * ld));
+  if (a->event_record_capacity) chk(alloc(&c.rec, 2 * (int64_t)a->event_record_capacity * ld));
+  if (err != hipSuccess)
+    return fail(ODE_ENOMEM, "allocating the probe copies: %s", hipGetErrorString(err));
+  ode_solve_args pa = *a;
+  pa.time_domain = c.td;
+  pa.state = c.y;
+  pa.accessories = c.acc;
+  pa.next_h = c.next_h;
+  pa.status = c.status;
+  pa.counts = c.counts;
+  pa.event_counts = c.evc;
+  pa.event_records = c.rec;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  chk(hipEventCreate(&ev0));
+  chk(hipEventCreate(&ev1));
+  if (err != hipSuccess) {
+    if (ev0) (void)hipEventDestroy(ev0);
+    return hip_fail(err, "hipEventCreate");
+  }
+  const int saved_block = e->block, saved_cap = e->cap;
+  // one probe: fresh copies of the inputs, then the timed solve
+  auto probe = [&](int block, int cap, double *ms) -> int {
+    e->block = block;
+    e->cap = cap;
+    hipError_t x = launch_probe_horizon(a->time_domain, c.td, ld, a->n_systems, a->system_index,
+                                        probe_fraction, st);
+    if (x == hipSuccess)
+      x = hipMemcpyAsync(c.y, a->state, sizeof(double) * e->n_state * ld,
+                         hipMemcpyDeviceToDevice, st);
+    if (x == hipSuccess && a->next_h)
+      x = hipMemcpyAsync(c.next_h, a->next_h, sizeof(double) * ld, hipMemcpyDeviceToDevice, st);
+    if (x != hipSuccess) return hip_fail(x, "preparing a probe");
+    Params prm;
+    int nev = 0, nacc = 0, grid = 0;
+    int r = prepare_launch(e, &pa, prm, nev, nacc, grid);
+    if (r != ODE_OK) return r;
+    x = hipEventRecord(ev0, st);
+    if (x == hipSuccess)
+      x = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid, block, st);
+    if (x == hipSuccess) x = hipEventRecord(ev1, st);
+    if (x == hipSuccess) x = hipEventSynchronize(ev1);
+    float f = 0.0f;
+    if (x == hipSuccess) x = hipEventElapsedTime(&f, ev0, ev1);
+    if (x != hipSuccess) return hip_fail(x, "timing a probe");
+    *ms = f;
+    return ODE_OK;
+  };
+
+  int best_block = saved_block, best_cap = saved_cap, n_tried = 0;
+  double best = 0.0, base = 0.0;
+  // the handle's own configuration, twice: the first run also warms up
+  rc = probe(saved_block, saved_cap, &base);
+  if (rc == ODE_OK) rc = probe(saved_block, saved_cap, &base);
+  best = base;
+  n_tried = 1;
+  static const int kBlocks[] = {64, 128, 256};
+  for (int b : kBlocks) {
+    int full = 0;
+    e->cap = 0;
+    rc = query_blocks(e, b, event_slots(a->n_events), acc_slots(a->n_accessories), &full);
+    for (int half = 0; half < 2 && rc == ODE_OK; ++half) {
+      const int cap = half ? full / 2 : 0;
+      if (half && cap < 1) continue;
+      if (b == saved_block && cap == saved_cap) continue;
+      double ms = 0.0;
+      rc = probe(b, cap, &ms);
+      ++n_tried;
+      if (rc == ODE_OK && ms < best) {
+        best = ms;
+        best_block = b;
+        best_cap = cap;
+      }
+    }
+    if (rc != ODE_OK) break;
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  e->block = rc == ODE_OK ? best_block : saved_block;
+  e->cap = rc == ODE_OK ? best_cap : saved_cap;
+  e->last_blocks_per_cu = 0;  // describe the chosen configuration, not the last probe
+  e->last_grid = 0;
+  if (rc != ODE_OK) return rc;
+  result->block_size = best_block;
+  result->blocks_per_cu = best_cap;
+  result->candidates = n_tried;
+  result->best_ms = best;
+  result->default_ms = base;
   return ODE_OK;
 }
 

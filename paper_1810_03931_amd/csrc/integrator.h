@@ -30,8 +30,9 @@ struct EventCtl {
 };
 
 struct AccCtl {
-  int32_t kind, component;  // kind: 1 max, 2 min
+  int32_t kind, component;  // kind: 1 max, 2 min, 3 log-and-reset at sections
 };
+constexpr int32_t kAccMax = 1, kAccMin = 2, kAccLogReset = 3;
 
 // Solver-wide constants.  Passed by value: they live in the kernel-argument
 // segment and every wave reads them into scalar registers, so the per-lane
@@ -39,6 +40,7 @@ struct AccCtl {
 struct Control {
   double rtol[kMaxState], atol[kMaxState];
   double h0, h_min, h_max, grow, shrink, t_record;
+  double section_period;  // > 0: Poincare sections n*T are forced boundaries
   int32_t max_steps;
   int32_t max_eq;
   int32_t n_events, n_acc, rec_cap, pad;
@@ -59,6 +61,7 @@ struct Arrays {
   int32_t *evc;
   double *rec;
   const int64_t *index;
+  const double *t_rec;  // per-system window start, or nullptr (Control::t_record)
   int64_t n, ld;
   unsigned long long *queue;  // [0] next queue position, [1] finished waves
   uint32_t total_waves;
@@ -81,5 +84,18 @@ const void *integrator_kernel(int model, int method, int prec, int nev, int nacc
 // Launch it with `grid` workgroups of `block` threads on `stream`.
 hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc,
                              const Params &prm, int grid, int block, hipStream_t stream);
+
+// Repeated-horizon helpers (segments.hip): set t1 = t0 + segment for every
+// listed system, and copy the state and accessories of every listed system
+// into one snapshot.
+hipError_t launch_set_horizon(double *td, int64_t ld, int64_t n, const int64_t *index,
+                              double segment, hipStream_t stream);
+// t1 of the copy = t0 + fraction * (t1 - t0) for every listed system (the
+// probe horizon of the autotuner); fraction 1 copies t1 unchanged.
+hipError_t launch_probe_horizon(const double *td_src, double *td_dst, int64_t ld, int64_t n,
+                                const int64_t *index, double fraction, hipStream_t stream);
+hipError_t launch_snapshot(const double *y, int n_state, const double *acc, int n_acc_rows,
+                           int64_t ld, int64_t n, const int64_t *index, double *out,
+                           hipStream_t stream);
 
 }  // namespace odeens

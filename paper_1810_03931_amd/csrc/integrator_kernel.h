@@ -130,17 +130,18 @@ __device__ __forceinline__ void cash_karp_attempt(double t, const double (&y)[M:
   }
 }
 
-// Mixed precision (NEXT-1 of the design): the right-hand side and the stage
-// sums run in FP32, the state, time, step and the error estimate in FP64.
-// Each stage input is y + h * (FP32 sum) formed in FP64 and rounded once to
-// FP32; the propagated solution adds the FP32 weighted sum to y in FP64; the
-// error estimate h * sum e_i k_i is formed in FP64 from the FP32 stage
-// derivatives, so it carries their rounding (~6e-8 relative) but no
-// cancellation.
+// Mixed precision: the right-hand side and the stage sums run in FP32, the
+// state, time, step and the error estimate in FP64.  Each stage input
+// y + h * (FP32 sum) is formed in FP64 and handed to the model, which rounds
+// to FP32 what it uses (after forming in FP64 any difference that would
+// cancel in FP32, or reducing a large angle); the propagated solution adds the
+// FP32 weighted sum to y in FP64; the error estimate h * sum e_i k_i is formed
+// in FP64 from the FP32 stage derivatives, so it carries their rounding
+// (~6e-8 relative) but no cancellation.
 template <class M>
 __device__ __forceinline__ void cash_karp_attempt_mixed(double t, const double (&y)[M::NS],
                                                         const double (&p)[M::NP],
-                                                        const float (&q)[M::NP], double h,
+                                                        const float (&q)[M::NQ], double h,
                                                         double (&y5)[M::NS],
                                                         double (&err)[M::NS]) {
   constexpr int N = M::NS;
@@ -149,37 +150,33 @@ __device__ __forceinline__ void cash_karp_attempt_mixed(double t, const double (
                         stage_time(t, ck::c4, h), t + h, stage_time(t, ck::c6, h)};
   float F[6][FW];
   M::template forcing32<6>(ts, p, F);
-  float k1[N], k2[N], k3[N], k4[N], k5[N], k6[N], ys[N];
+  float k1[N], k2[N], k3[N], k4[N], k5[N], k6[N];
+  double ys[N];
+  M::rhs32(y, q, F[0], k1);
 #pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(y[i]);
-  M::rhs32(ys, q, F[0], k1);
-#pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(h, double(ckf::a21 * k1[i]), y[i]));
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, double(ckf::a21 * k1[i]), y[i]);
   M::rhs32(ys, q, F[1], k2);
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-    ys[i] = static_cast<float>(fma(h, double(fmaf(ckf::a32, k2[i], ckf::a31 * k1[i])), y[i]));
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, double(fmaf(ckf::a32, k2[i], ckf::a31 * k1[i])), y[i]);
   M::rhs32(ys, q, F[2], k3);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    ys[i] = static_cast<float>(
-        fma(h, double(fmaf(ckf::a43, k3[i], fmaf(ckf::a42, k2[i], ckf::a41 * k1[i]))), y[i]));
+    ys[i] = fma(h, double(fmaf(ckf::a43, k3[i], fmaf(ckf::a42, k2[i], ckf::a41 * k1[i]))), y[i]);
   M::rhs32(ys, q, F[3], k4);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    ys[i] = static_cast<float>(fma(
-        h,
-        double(fmaf(ckf::a54, k4[i], fmaf(ckf::a53, k3[i], fmaf(ckf::a52, k2[i], ckf::a51 * k1[i])))),
-        y[i]));
+    ys[i] = fma(h,
+                double(fmaf(ckf::a54, k4[i],
+                            fmaf(ckf::a53, k3[i], fmaf(ckf::a52, k2[i], ckf::a51 * k1[i])))),
+                y[i]);
   M::rhs32(ys, q, F[4], k5);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    ys[i] = static_cast<float>(fma(
-        h,
-        double(fmaf(ckf::a65, k5[i],
-                    fmaf(ckf::a64, k4[i],
-                         fmaf(ckf::a63, k3[i], fmaf(ckf::a62, k2[i], ckf::a61 * k1[i]))))),
-        y[i]));
+    ys[i] = fma(h,
+                double(fmaf(ckf::a65, k5[i],
+                            fmaf(ckf::a64, k4[i],
+                                 fmaf(ckf::a63, k3[i], fmaf(ckf::a62, k2[i], ckf::a61 * k1[i]))))),
+                y[i]);
   M::rhs32(ys, q, F[5], k6);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -195,7 +192,7 @@ __device__ __forceinline__ void cash_karp_attempt_mixed(double t, const double (
 template <class M>
 __device__ __forceinline__ void rk4_attempt_mixed(double t, const double (&y)[M::NS],
                                                   const double (&p)[M::NP],
-                                                  const float (&q)[M::NP], double h,
+                                                  const float (&q)[M::NQ], double h,
                                                   double (&yn)[M::NS]) {
   constexpr int N = M::NS;
   constexpr int FW = M::NF > 0 ? M::NF : 1;
@@ -203,18 +200,17 @@ __device__ __forceinline__ void rk4_attempt_mixed(double t, const double (&y)[M:
   const double ts[3] = {t, t + hh, t + h};
   float F[3][FW];
   M::template forcing32<3>(ts, p, F);
-  float k1[N], k2[N], k3[N], k4[N], ys[N];
+  float k1[N], k2[N], k3[N], k4[N];
+  double ys[N];
+  M::rhs32(y, q, F[0], k1);
 #pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(y[i]);
-  M::rhs32(ys, q, F[0], k1);
-#pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(hh, double(k1[i]), y[i]));
+  for (int i = 0; i < N; ++i) ys[i] = fma(hh, double(k1[i]), y[i]);
   M::rhs32(ys, q, F[1], k2);
 #pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(hh, double(k2[i]), y[i]));
+  for (int i = 0; i < N; ++i) ys[i] = fma(hh, double(k2[i]), y[i]);
   M::rhs32(ys, q, F[1], k3);
 #pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = static_cast<float>(fma(h, double(k3[i]), y[i]));
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, double(k3[i]), y[i]);
   M::rhs32(ys, q, F[2], k4);
   const double h6 = h * (1.0 / 6.0);
 #pragma unroll
@@ -315,6 +311,7 @@ __device__ __forceinline__ Arrays arrays_of(ParamsRef q) {
   a.evc = q->a.evc;
   a.rec = q->a.rec;
   a.index = q->a.index;
+  a.t_rec = q->a.t_rec;
   a.n = q->a.n;
   a.ld = q->a.ld;
   a.queue = q->a.queue;
@@ -349,12 +346,16 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   int64_t s = -1;
   bool active = false;
   double t = 0.0, t1 = 0.0, h = 0.0;
+  double t_rec = 0.0;  // start of this system's recording window
   double y[N], p[P];
-  float pf[PREC == kPrecMixed ? P : 1];  // FP32 copy of the parameters (mixed precision)
+  constexpr int Q = PREC == kPrecMixed ? M::NQ : 1;
+  float pf[Q];  // FP32 parameters of the mixed-precision right-hand side
   int32_t attempts = 0, n_acc = 0, n_rej = 0, flags = 0, status = kRunning;
   bool window_open = false;
   double accv[AC], acct[AC];
   double seg_start = 0.0;  // RK4: the state after m steps of a segment is at seg_start + m*dt
+  // index n of the next Poincare section n*T (an integer held in FP64)
+  double sec_n = 0.0;
   int32_t seg_steps = 0;
   double F[EV];
   int32_t zone[EV], cnt[EV], wcnt[EV];
@@ -372,7 +373,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
   for (int j = 0; j < P; ++j) p[j] = 0.0;
 #pragma unroll
-  for (int j = 0; j < (PREC == kPrecMixed ? P : 1); ++j) pf[j] = 0.0f;
+  for (int j = 0; j < Q; ++j) pf[j] = 0.0f;
 #pragma unroll
   for (int j = 0; j < EV; ++j) F[j] = 0.0, zone[j] = cnt[j] = wcnt[j] = 0;
 #pragma unroll
@@ -384,8 +385,13 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
     for (int k = 0; k < NACC; ++k)
       if (k < c.n_acc) {
-        accv[k] = pick(y, c.acc[k].component);
-        acct[k] = t;
+        if (c.acc[k].kind == kAccLogReset) {
+          accv[k] = 0.0;  // sum of ln y[c] at the sections
+          acct[k] = 0.0;  // number of sections added
+        } else {
+          accv[k] = pick(y, c.acc[k].component);
+          acct[k] = t;
+        }
       }
   };
 
@@ -443,13 +449,13 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             // ---- load and initialise the system ----
             t = a.td[s];
             t1 = a.td[ld + s];
+            t_rec = a.t_rec ? a.t_rec[s] : c.t_record;
 #pragma unroll
             for (int i = 0; i < N; ++i) y[i] = a.y[i * ld + s];
 #pragma unroll
             for (int j = 0; j < P; ++j) p[j] = a.p[j * ld + s];
             if constexpr (PREC == kPrecMixed) {
-#pragma unroll
-              for (int j = 0; j < P; ++j) pf[j] = static_cast<float>(p[j]);
+              M::prepare32(p, pf);
             }
             attempts = n_acc = n_rej = flags = 0;
             status = kRunning;
@@ -478,11 +484,21 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
               }
             }
             window_open = false;
+            sec_n = 0.0;
             if (!isfinite(t) || !isfinite(t1)) {
               status = kBadInput;
-            } else if (c.t_record <= t) {
-              window_open = true;
-              acc_init();
+            } else {
+              // Poincare sections n*T count from time zero; the first one is
+              // the first rounded product strictly after t (paper Sec. 2.1)
+              const double T = c.section_period;
+              if (T > 0.0) {
+                sec_n = floor(t / T) + 1.0;
+                for (int it = 0; it < 3 && __dmul_rn(sec_n, T) <= t; ++it) sec_n += 1.0;
+              }
+              if (t_rec <= t) {
+                window_open = true;
+                acc_init();
+              }
             }
             if (status == kRunning && t >= t1) status = kDone;
             if (status != kRunning) retire();
@@ -502,7 +518,11 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     if (locating) {
       h_att = sc;
     } else {
-      t_b = (!window_open && c.t_record < t1) ? c.t_record : t1;
+      t_b = (!window_open && t_rec < t1) ? t_rec : t1;
+      if (c.section_period > 0.0) {
+        const double t_sec = __dmul_rn(sec_n, c.section_period);
+        t_b = (t_sec < t_b) ? t_sec : t_b;
+      }
       if (METHOD == kMethodRK4) {
         const double t_grid = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), c.h0));
         if (t_grid >= __dsub_rn(t_b, __dmul_rn(1e-9, c.h0))) {
@@ -674,16 +694,16 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       // ordinary accessories (paper Sec. 6.7) inside the recording window,
       // initialised when it opens (Sec. 6.8)
       if (!window_open) {
-        if (t >= c.t_record) {
+        if (t >= t_rec) {
           window_open = true;
           acc_init();
         }
       } else {
 #pragma unroll
         for (int k = 0; k < NACC; ++k)
-          if (k < c.n_acc) {
+          if (k < c.n_acc && c.acc[k].kind != kAccLogReset) {
             const double v = pick(y, c.acc[k].component);
-            const bool better = (c.acc[k].kind == 1) ? (v > accv[k]) : (v < accv[k]);
+            const bool better = (c.acc[k].kind == kAccMax) ? (v > accv[k]) : (v < accv[k]);
             accv[k] = better ? v : accv[k];
             acct[k] = better ? t : acct[k];
           }
@@ -715,6 +735,22 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
           }
           if (e.stop_after > 0 && cnt[j] == e.stop_after) status = kStopEvent;
         }
+      }
+      // Poincare section reached (the step was clipped to it): the Lyapunov
+      // accumulators add ln y[c] for sections after the window start, and
+      // y[c] restarts from 1 at every section (paper Sec. 2.1)
+      if (c.section_period > 0.0 && t == __dmul_rn(sec_n, c.section_period)) {
+#pragma unroll
+        for (int k = 0; k < NACC; ++k)
+          if (k < c.n_acc && c.acc[k].kind == kAccLogReset) {
+            const int comp = c.acc[k].component;
+            if (window_open && t > t_rec) {
+              accv[k] = accv[k] + log(pick(y, comp));
+              acct[k] = acct[k] + 1.0;
+            }
+            put(y, comp, 1.0);
+          }
+        sec_n += 1.0;
       }
       // zone states: normal exactly when outside the zone; accepted steps
       // that stay inside after a detection count towards the equilibrium stop

@@ -70,6 +70,38 @@ __device__ __forceinline__ float cos_turns(double turns) {
 }
 constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
 
+// FP32 ln(1 + x) and exp(z) - 1 with small relative error also where the
+// result is small (the mixed-precision Keller-Miksis pressure balance needs
+// both near x = z = 0).  Near zero: ln(1 + x) = 2 atanh(s), s = x / (2 + x),
+// by its odd series through s^7 (|x| < 1/4 gives |s| < 1/9, truncation
+// < 3e-9 relative); exp(z) - 1 by Taylor's series through z^7 (|z| < 1/4,
+// truncation < 2e-9 relative).  Elsewhere the hardware log2 / exp2.
+__device__ __forceinline__ float log1p32(float x) {
+  if (fabsf(x) < 0.25f) {
+    const float s = x * __builtin_amdgcn_rcpf(2.0f + x);
+    const float s2 = s * s;
+    const float poly = fmaf(s2, fmaf(s2, fmaf(s2, 1.0f / 7.0f, 1.0f / 5.0f), 1.0f / 3.0f), 1.0f);
+    return 2.0f * s * poly;
+  }
+  return __builtin_amdgcn_logf(1.0f + x) * 0.69314718055994530942f;
+}
+__device__ __forceinline__ float expm1_32(float z) {
+  if (fabsf(z) < 0.25f) {
+    float e = fmaf(z, 1.0f / 7.0f, 1.0f);
+    e = fmaf(z * (1.0f / 6.0f), e, 1.0f);
+    e = fmaf(z * (1.0f / 5.0f), e, 1.0f);
+    e = fmaf(z * (1.0f / 4.0f), e, 1.0f);
+    e = fmaf(z * (1.0f / 3.0f), e, 1.0f);
+    e = fmaf(z * 0.5f, e, 1.0f);
+    return z * e;
+  }
+  return __builtin_amdgcn_exp2f(z * 1.44269504088896340736f) - 1.0f;
+}
+
+// Every model's mixed-precision right-hand side receives the stage state in
+// FP64 and its FP32 parameters `q` (`prepare32` derives them from the FP64
+// parameters once per system).
+
 // Duffing oscillator, paper Sec. 2.1 Eqs. (1)-(2), with linear and cubic
 // stiffness as parameters: p = (k, B, omega, lin, cub),
 //   y1' = y2,  y2' = -lin*y1 - cub*y1^3 - k*y2 + B*cos(omega*t).
@@ -78,6 +110,7 @@ struct Duffing {
   static constexpr int NS = 2;
   static constexpr int NP = 5;
   static constexpr int NF = 1;
+  static constexpr int NQ = 5;
   static constexpr int ID = 1;
   template <int S>
   __device__ __forceinline__ static void forcing(const double (&ts)[S], const double (&p)[NP],
@@ -106,12 +139,75 @@ struct Duffing {
 #pragma unroll
     for (int k = 0; k < S; ++k) F[k][0] = cos_turns(__dmul_rn(p[2], ts[k]) * kInvTwoPi);
   }
-  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&p)[NP],
+  __device__ __forceinline__ static void prepare32(const double (&p)[NP], float (&q)[NQ]) {
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) q[j] = static_cast<float>(p[j]);
+  }
+  __device__ __forceinline__ static void rhs32(const double (&y)[NS], const float (&p)[NQ],
                                                const float (&F)[NF], float (&f)[NS]) {
-    const float y1 = y[0], y2 = y[1];
+    const float y1 = static_cast<float>(y[0]), y2 = static_cast<float>(y[1]);
     const float spring = fmaf(p[4] * y1 * y1, y1, fmaf(p[3], y1, p[0] * y2));
     f[0] = y2;
     f[1] = fmaf(p[1], F[0], -spring);
+  }
+};
+
+// Duffing oscillator with its linearisation in polar coordinates attached,
+// paper Sec. 2.1 Eqs. (3)-(6): the tangent vector r (cos phi, sin phi) of the
+// Duffing flow evolves with g1 = dF2/dy1 = -lin - 3 cub y1^2 and
+// g2 = dF2/dy2 = -k:
+//   r'   = r ((1 + g1) sin(phi) cos(phi) + g2 sin(phi)^2)
+//   phi' = -sin(phi)^2 + (g1 cos(phi) + g2 sin(phi)) cos(phi).
+// y = (y1, y2, r, phi), p = (k, B, omega, lin, cub) as for Duffing.  The
+// angle is state-dependent, so its sine and cosine are evaluated per stage
+// (the paper also computes them once per evaluation and reuses them).
+struct DuffingLyapunov {
+  static constexpr int NS = 4;
+  static constexpr int NP = 5;
+  static constexpr int NF = 1;
+  static constexpr int NQ = 5;
+  static constexpr int ID = 5;
+  template <int S>
+  __device__ __forceinline__ static void forcing(const double (&ts)[S], const double (&p)[NP],
+                                                 double (&F)[S][NF]) {
+    Duffing::forcing<S>(ts, p, F);
+  }
+  __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&p)[NP],
+                                             const double (&F)[NF], double (&f)[NS]) {
+    const double y1 = y[0], y2 = y[1], r = y[2];
+    const double spring = fma(p[4] * y1 * y1, y1, fma(p[3], y1, p[0] * y2));
+    f[0] = y2;
+    f[1] = fma(p[1], F[0], -spring);
+    const double g1 = fma(-3.0 * p[4], y1 * y1, -p[3]);
+    const double g2 = -p[0];
+    double sn, cs;
+    sincos(y[3], &sn, &cs);
+    f[2] = r * sn * fma(1.0 + g1, cs, g2 * sn);
+    f[3] = fma(fma(g1, cs, g2 * sn), cs, -sn * sn);
+  }
+  template <int S>
+  __device__ __forceinline__ static void forcing32(const double (&ts)[S], const double (&p)[NP],
+                                                   float (&F)[S][NF]) {
+    Duffing::forcing32<S>(ts, p, F);
+  }
+  __device__ __forceinline__ static void prepare32(const double (&p)[NP], float (&q)[NQ]) {
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) q[j] = static_cast<float>(p[j]);
+  }
+  __device__ __forceinline__ static void rhs32(const double (&y)[NS], const float (&p)[NQ],
+                                               const float (&F)[NF], float (&f)[NS]) {
+    const float y1 = static_cast<float>(y[0]), y2 = static_cast<float>(y[1]);
+    const float r = static_cast<float>(y[2]);
+    const float spring = fmaf(p[4] * y1 * y1, y1, fmaf(p[3], y1, p[0] * y2));
+    f[0] = y2;
+    f[1] = fmaf(p[1], F[0], -spring);
+    const float g1 = fmaf(-3.0f * p[4], y1 * y1, -p[3]);
+    const float g2 = -p[0];
+    // the angle grows without bound: reduce it in FP64 (in revolutions)
+    const double turns = y[3] * kInvTwoPi;
+    const float sn = sin_turns(turns), cs = cos_turns(turns);
+    f[2] = r * sn * fmaf(1.0f + g1, cs, g2 * sn);
+    f[3] = fmaf(fmaf(g1, cs, g2 * sn), cs, -sn * sn);
   }
 };
 
@@ -123,6 +219,7 @@ struct KellerMiksis {
   static constexpr int NS = 2;
   static constexpr int NP = 13;
   static constexpr int NF = 4;
+  static constexpr int NQ = 14;
   static constexpr int ID = 2;
   template <int S>
   __device__ __forceinline__ static void forcing(const double (&ts)[S], const double (&C)[NP],
@@ -176,24 +273,41 @@ struct KellerMiksis {
       F[k][3] = cos_turns(r2);
     }
   }
-  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&C)[NP],
+  // FP32 parameters: C0..C12 and, in slot 13, the pressure imbalance at rest
+  // E0 = C0 - C2 - C3 (zero up to rounding: the gas pressure balances the
+  // static pressure and surface tension at R = R_E).
+  __device__ __forceinline__ static void prepare32(const double (&C)[NP], float (&q)[NQ]) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) q[j] = static_cast<float>(C[j]);
+    q[13] = static_cast<float>((C[0] - C[2]) - C[3]);
+  }
+  // Near rest the gas term C0 (R_E/R)^C10 and the static terms C2 + C3 R_E/R
+  // are large (C0 reaches ~1e6 for micrometre bubbles at 20 kHz) and nearly
+  // cancel, so FP32 rounding of each would swamp the net pressure.  They are
+  // regrouped as C0 ((R_E/R)^C10 - 1) - C3 (R_E/R - 1) + E0 with
+  // (R_E/R)^C10 - 1 = expm1(-C10 ln(1 + d)), d = y1 - 1 formed in FP64, so the
+  // FP32 rounding error is proportional to the distance from rest.
+  __device__ __forceinline__ static void rhs32(const double (&y)[NS], const float (&C)[NQ],
                                                const float (&F)[NF], float (&f)[NS]) {
-    const float y1 = y[0], y2 = y[1];
-    const float rx = 1.0f / y1;
-    const float gas = __builtin_amdgcn_exp2f(C[10] * __builtin_amdgcn_logf(rx));
+    const float y1 = static_cast<float>(y[0]), y2 = static_cast<float>(y[1]);
+    const float d = static_cast<float>(y[0] - 1.0);
+    const float rx = __builtin_amdgcn_rcpf(y1);
+    const float gas_m1 = expm1_32(-C[10] * log1p32(d));    // (R_E/R)^C10 - 1
+    const float rx_m1 = -d * rx;                            // R_E/R - 1
     const float u = fmaf(C[9], y2, 1.0f);
     const float forcing_p = fmaf(C[5], F[0], C[6] * F[2]);
     const float forcing_d = fmaf(C[7], F[1], C[8] * F[3]);
     const float inertia = fmaf(-C[9] * (1.0f / 3.0f), y2, 1.0f) * 1.5f * y2 * y2;
-    float N = fmaf(C[1], y2, C[0]) * gas;
-    N = fmaf(-C[2], u, N);
-    N = fmaf(-fmaf(C[4], y2, C[3]), rx, N);
+    // rest balance + the y2 terms of (C0 + C1 y2) gas - C2 (1 + C9 y2)
+    float N = fmaf(C[0], gas_m1, fmaf(-C[3], rx_m1, C[13]));
+    N = fmaf(y2, fmaf(C[1], 1.0f + gas_m1, -C[2] * C[9]), N);
+    N = fmaf(-C[4] * y2, rx, N);
     N -= inertia;
     N = fmaf(-forcing_p, u, N);
     N = fmaf(-y1, forcing_d, N);
     const float D = fmaf(-C[9] * y1, y2, y1) + C[4] * C[9];
     f[0] = y2;
-    f[1] = N / D;
+    f[1] = N * __builtin_amdgcn_rcpf(D);
   }
 };
 
@@ -203,6 +317,7 @@ struct ReliefValve {
   static constexpr int NS = 3;
   static constexpr int NP = 5;
   static constexpr int NF = 0;
+  static constexpr int NQ = 5;
   static constexpr int ID = 3;
   template <int S>
   __device__ __forceinline__ static void forcing(const double (&)[S], const double (&)[NP],
@@ -216,8 +331,14 @@ struct ReliefValve {
   template <int S>
   __device__ __forceinline__ static void forcing32(const double (&)[S], const double (&)[NP],
                                                    float (&)[S][1]) {}
-  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&p)[NP],
+  __device__ __forceinline__ static void prepare32(const double (&p)[NP], float (&q)[NQ]) {
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) q[j] = static_cast<float>(p[j]);
+  }
+  __device__ __forceinline__ static void rhs32(const double (&yd)[NS], const float (&p)[NQ],
                                                const float (&)[1], float (&f)[NS]) {
+    const float y[NS] = {static_cast<float>(yd[0]), static_cast<float>(yd[1]),
+                         static_cast<float>(yd[2])};
     f[0] = y[1];
     f[1] = fmaf(-p[0], y[1], y[2] - (y[0] + p[1]));
     f[2] = p[2] * fmaf(-y[0], sqrtf(y[2]), p[3]);
@@ -229,6 +350,7 @@ struct Ballistic {
   static constexpr int NS = 2;
   static constexpr int NP = 1;
   static constexpr int NF = 0;
+  static constexpr int NQ = 1;
   static constexpr int ID = 4;
   template <int S>
   __device__ __forceinline__ static void forcing(const double (&)[S], const double (&)[NP],
@@ -241,9 +363,12 @@ struct Ballistic {
   template <int S>
   __device__ __forceinline__ static void forcing32(const double (&)[S], const double (&)[NP],
                                                    float (&)[S][1]) {}
-  __device__ __forceinline__ static void rhs32(const float (&y)[NS], const float (&p)[NP],
+  __device__ __forceinline__ static void prepare32(const double (&p)[NP], float (&q)[NQ]) {
+    q[0] = static_cast<float>(p[0]);
+  }
+  __device__ __forceinline__ static void rhs32(const double (&y)[NS], const float (&p)[NQ],
                                                const float (&)[1], float (&f)[NS]) {
-    f[0] = y[1];
+    f[0] = static_cast<float>(y[1]);
     f[1] = -p[0];
   }
 };

@@ -18,10 +18,11 @@ from typing import Any, Sequence
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "lib", "libode_ensemble.so")
 
-MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4}
+MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4,
+         "duffing_lyapunov": 5}
 METHOD = {"rkck45": 0, "rk4": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
-ACC_KIND = {"max": 1, "min": 2}
+ACC_KIND = {"max": 1, "min": 2, "log_reset": 3}
 MAX_STATE, MAX_EVENTS, MAX_ACC = 8, 4, 4
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSUP = 0, -1, -2, -3, -4
@@ -50,7 +51,13 @@ class AccessorySpec(C.Structure):
 
 class Desc(C.Structure):
     _fields_ = [("model", C.c_int32), ("method", C.c_int32), ("precision", C.c_int32),
-                ("block_size", C.c_int32)]
+                ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("candidates", C.c_int32), ("reserved", C.c_int32),
+                ("best_ms", C.c_double), ("default_ms", C.c_double)]
 
 
 class SolveArgs(C.Structure):
@@ -59,11 +66,11 @@ class SolveArgs(C.Structure):
         ("time_domain", C.c_void_p), ("state", C.c_void_p), ("params", C.c_void_p),
         ("accessories", C.c_void_p), ("next_h", C.c_void_p), ("status", C.c_void_p),
         ("counts", C.c_void_p), ("event_counts", C.c_void_p), ("event_records", C.c_void_p),
-        ("system_index", C.c_void_p),
+        ("system_index", C.c_void_p), ("record_start", C.c_void_p),
         ("rtol", C.c_double * MAX_STATE), ("atol", C.c_double * MAX_STATE),
         ("h0", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
         ("grow", C.c_double), ("shrink", C.c_double), ("t_record", C.c_double),
-        ("max_steps", C.c_int64), ("max_equilibrium_steps", C.c_int32),
+        ("section_period", C.c_double), ("max_steps", C.c_int64), ("max_equilibrium_steps", C.c_int32),
         ("n_events", C.c_int32), ("n_accessories", C.c_int32),
         ("event_record_capacity", C.c_int32),
         ("events", EventSpec * MAX_EVENTS), ("accessory_specs", AccessorySpec * MAX_ACC),
@@ -77,7 +84,8 @@ class Info(C.Structure):
 
 
 EXPORTS = ("ode_ensemble_model_dims", "ode_ensemble_create", "ode_ensemble_solve",
-           "ode_ensemble_query", "ode_ensemble_destroy", "ode_ensemble_last_error")
+           "ode_ensemble_solve_segments", "ode_ensemble_tune", "ode_ensemble_query",
+           "ode_ensemble_destroy", "ode_ensemble_last_error")
 
 _lib = None
 
@@ -96,6 +104,12 @@ def load_library(path: str = LIB_PATH):
     L.ode_ensemble_create.restype = C.c_int
     L.ode_ensemble_solve.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_void_p]
     L.ode_ensemble_solve.restype = C.c_int
+    L.ode_ensemble_solve_segments.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_int32,
+                                              C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
+    L.ode_ensemble_solve_segments.restype = C.c_int
+    L.ode_ensemble_tune.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_double, C.c_void_p,
+                                    C.POINTER(TuneResult)]
+    L.ode_ensemble_tune.restype = C.c_int
     L.ode_ensemble_query.argtypes = [C.c_void_p, C.POINTER(Info)]
     L.ode_ensemble_query.restype = C.c_int
     L.ode_ensemble_destroy.argtypes = [C.c_void_p]
@@ -134,7 +148,8 @@ def _ptr(t, dtype, rows: int, ld: int, name: str):
 
 def fill_args(args: SolveArgs, n_state: int, *, h0: float, rtol=1e-10, atol=1e-10,
               h_min: float = 1e-12, h_max: float = 1e6, grow: float = 5.0, shrink: float = 0.1,
-              t_record: float = float("-inf"), max_steps: int = 10**8,
+              t_record: float = float("-inf"), section_period: float = 0.0,
+              max_steps: int = 10**8,
               max_equilibrium_steps: int = 0, events: Sequence[dict] = (),
               accessories: Sequence[tuple] = (), record_cap: int = 0) -> None:
     """Scalar options and specs of one solve (paper Sec. 6.4-6.7)."""
@@ -144,6 +159,7 @@ def fill_args(args: SolveArgs, n_state: int, *, h0: float, rtol=1e-10, atol=1e-1
         args.rtol[i], args.atol[i] = float(rt[i]), float(at[i])
     args.h0, args.h_min, args.h_max = float(h0), float(h_min), float(h_max)
     args.grow, args.shrink, args.t_record = float(grow), float(shrink), float(t_record)
+    args.section_period = float(section_period)
     args.max_steps, args.max_equilibrium_steps = int(max_steps), int(max_equilibrium_steps)
     if len(events) > MAX_EVENTS or len(accessories) > MAX_ACC:
         raise ValueError("too many events or accessories")
@@ -169,11 +185,13 @@ class Ensemble:
     """A solver handle for one (model, method, precision) on the current
     device (paper Sec. 6.2)."""
 
-    def __init__(self, model: str, method: str, precision: str = "fp64", block_size: int = 0):
+    def __init__(self, model: str, method: str, precision: str = "fp64", block_size: int = 0,
+                 blocks_per_cu: int = 0):
         L = load_library()
         self.model, self.method = model, method
         self.n_state, self.n_param = model_dims(model)
-        d = Desc(MODEL[model], METHOD[method], PRECISION.get(precision, -1), block_size)
+        d = Desc(MODEL[model], METHOD[method], PRECISION.get(precision, -1), block_size,
+                 blocks_per_cu)
         h = C.c_void_p()
         _check(L.ode_ensemble_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -211,17 +229,10 @@ class Ensemble:
         }
         return out
 
-    def solve(self, time_domain, state, params, *, next_h=None, system_index=None, out=None,
-              stream=None, **options: Any) -> dict:
-        """Enqueue one integration on ``stream`` (default: torch's current
-        stream) and return the output tensors (written asynchronously).
-
-        ``time_domain`` [2, ld], ``state`` [n_state, ld] and ``next_h`` [ld]
-        are updated in place; ``params`` [n_param, ld] is read.  Options:
-        h0, rtol, atol, h_min, h_max, grow, shrink, t_record, max_steps,
-        max_equilibrium_steps, events, accessories, record_cap.
-        """
+    def _args(self, time_domain, state, params, next_h, system_index, out, options):
         import torch
+        options = dict(options)
+        record_start = options.pop("record_start", None)
         ld = int(time_domain.shape[-1])
         events = list(options.get("events", ()))
         accs = list(options.get("accessories", ()))
@@ -253,10 +264,72 @@ class Ensemble:
             if system_index.dtype != i64 or not system_index.is_cuda or not system_index.is_contiguous():
                 raise ValueError("system_index: need a contiguous int64 CUDA tensor")
             a.system_index = system_index.data_ptr() if n else None
+        if record_start is not None:
+            a.record_start = _ptr(record_start, torch.float64, 1, ld, "record_start")
         fill_args(a, self.n_state, **options)
+        return a, out, len(accs)
+
+    def solve(self, time_domain, state, params, *, next_h=None, system_index=None, out=None,
+              stream=None, **options: Any) -> dict:
+        """Enqueue one integration on ``stream`` (default: torch's current
+        stream) and return the output tensors (written asynchronously).
+
+        ``time_domain`` [2, ld], ``state`` [n_state, ld] and ``next_h`` [ld]
+        are updated in place; ``params`` [n_param, ld] is read.  Options:
+        h0, rtol, atol, h_min, h_max, grow, shrink, t_record, section_period,
+        max_steps, max_equilibrium_steps, events, accessories, record_cap.
+        """
+        import torch
+        a, out, _ = self._args(time_domain, state, params, next_h, system_index, out, options)
         if stream is None:
             stream = torch.cuda.current_stream(time_domain.device)
         _check(load_library().ode_ensemble_solve(self._h, C.byref(a), C.c_void_p(stream.cuda_stream)))
+        return out
+
+    def tune(self, time_domain, state, params, *, probe_fraction: float = 1.0, next_h=None,
+             system_index=None, stream=None, **options: Any) -> dict:
+        """Time the candidate launch configurations on private copies of the
+        problem (the arguments are only read) and keep the fastest on this
+        handle; returns the choice and the probe times."""
+        import torch
+        a, _, _ = self._args(time_domain, state, params, next_h, system_index, None, options)
+        if stream is None:
+            stream = torch.cuda.current_stream(time_domain.device)
+        r = TuneResult()
+        _check(load_library().ode_ensemble_tune(self._h, C.byref(a), float(probe_fraction),
+                                                C.c_void_p(stream.cuda_stream), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in TuneResult._fields_ if f != "reserved"}
+
+    def solve_segments(self, time_domain, state, params, n_segments: int, segment: float, *,
+                       first_snapshot: int = 0, snapshots=None, next_h=None, system_index=None,
+                       out=None, stream=None, **options: Any) -> dict:
+        """``n_segments`` consecutive solves, each from the current time over
+        ``segment`` more time units, recorded once as a HIP graph (paper
+        Sec. 7: a sweep advanced one excitation period per solve).  Snapshots
+        [n_segments - first_snapshot, n_state + 2*n_accessories, ld] of the
+        state and the accessories after each segment from ``first_snapshot``
+        on are returned in ``out["snapshots"]``."""
+        import torch
+        a, out, n_acc = self._args(time_domain, state, params, next_h, system_index, out, options)
+        ld = int(time_domain.shape[-1])
+        n_snap = int(n_segments) - int(first_snapshot)
+        rows = self.n_state + 2 * n_acc
+        valid = 0 <= int(first_snapshot) <= int(n_segments)   # else the library says EINVAL
+        if snapshots is None and n_snap > 0 and valid:
+            snapshots = torch.full((n_snap, rows, ld), float("nan"), dtype=torch.float64,
+                                   device=time_domain.device)
+        if valid and snapshots is not None and (
+                snapshots.dtype != torch.float64 or not snapshots.is_contiguous()
+                or snapshots.numel() < n_snap * rows * ld):
+            raise ValueError("snapshots: need a contiguous float64 tensor of "
+                             f"[{n_snap}, {rows}, {ld}]")
+        if stream is None:
+            stream = torch.cuda.current_stream(time_domain.device)
+        snap_ptr = C.c_void_p(snapshots.data_ptr() if (snapshots is not None and n_snap > 0) else None)
+        _check(load_library().ode_ensemble_solve_segments(
+            self._h, C.byref(a), int(n_segments), float(segment), int(first_snapshot), snap_ptr,
+            C.c_void_p(stream.cuda_stream)))
+        out["snapshots"] = snapshots
         return out
 
 

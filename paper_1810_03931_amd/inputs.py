@@ -33,7 +33,8 @@ MU_L = 8.902e-4        # Pa s (the paper prints "8.902^{-4}"; read as 8.902e-4)
 P_INF = 1.0e5          # Pa (1 bar)
 GAMMA = 1.4            # polytropic exponent
 
-MODELS = {"duffing": (2, 5), "keller_miksis": (2, 13), "relief_valve": (3, 5), "ballistic": (2, 1)}
+MODELS = {"duffing": (2, 5), "keller_miksis": (2, 13), "relief_valve": (3, 5), "ballistic": (2, 1),
+          "duffing_lyapunov": (4, 5)}
 
 
 @dataclasses.dataclass
@@ -154,6 +155,30 @@ def duffing_rkck45_sweep(n_k: int = 512, n_B: int = 256) -> Problem:
     return Problem("duffing_rkck45", "duffing", "rkck45", td, state, params, opts)
 
 
+def duffing_lyapunov_sweep(n: int = 61440) -> Problem:
+    """Largest Lyapunov exponent of the double-well Duffing oscillator
+    x'' + k x' - x + x^3 = 0.3 cos(t) (paper Sec. 2.1 and its Duffing4 test),
+    Cash-Karp at rtol = atol = 1e-9.
+
+    k on a uniform grid over [0.2, 0.3]; initial state a seeded +-1e-3 jitter
+    around the origin, tangent vector r = 1 at angle 0; Poincare sections
+    every period 2 pi, where r is reset to 1; 1024 transient + 32 recorded
+    periods; the accumulator (sum ln r, count) over the recorded sections.
+    """
+    g = _rng(5)
+    i = np.arange(n, dtype=np.float64)
+    k = 0.2 + 0.1 * i / max(n - 1, 1)
+    params = np.stack([k, np.full(n, 0.3), np.ones(n), np.full(n, -1.0), np.ones(n)])
+    state = np.concatenate([g.uniform(-1e-3, 1e-3, size=(2, n)),
+                            np.ones((1, n)), np.zeros((1, n))])
+    T = TWO_PI
+    td = np.stack([np.zeros(n), np.full(n, 1056 * T)])
+    opts = dict(h0=1e-3, rtol=1e-9, atol=1e-9, h_min=1e-12, h_max=1e6, grow=5.0, shrink=0.1,
+                t_record=1024 * T, section_period=T, accessories=[("log_reset", 2)],
+                max_steps=2 * 10**7)
+    return Problem("duffing_lyapunov", "duffing_lyapunov", "rkck45", td, state, params, opts)
+
+
 def keller_miksis_sweep(n: int = 1 << 18, *, cluster: bool = True) -> Problem:
     """Dual-frequency Keller-Miksis bubble, Cash-Karp at rtol = atol = 1e-10.
 
@@ -212,12 +237,14 @@ CONFIGS = {
     "duffing_rkck45": duffing_rkck45_sweep,
     "keller_miksis": keller_miksis_sweep,
     "relief_valve": relief_valve_sweep,
+    "duffing_lyapunov": duffing_lyapunov_sweep,
 }
 
 
 def short_horizon(pb: Problem) -> Problem:
     """The same sweep over a short horizon with the window open from t0:
-    one forcing period for RK4 Duffing and Keller-Miksis, two for the others."""
+    one forcing period for RK4 Duffing and Keller-Miksis, two for the others
+    (two Poincare sections for the Lyapunov sweep)."""
     periods = {"duffing_rk4": 1, "keller_miksis": 1}.get(pb.name, 2)
     T = 1.0 if pb.model == "keller_miksis" else TWO_PI
     return pb.with_horizon(periods * T, t_record=0.0)
@@ -239,3 +266,60 @@ def stratified_sample(n: int, k: int, seed: int = 0) -> np.ndarray:
     edges = np.linspace(0, n, k + 1).astype(np.int64)
     return np.array([g.integers(edges[m], max(edges[m + 1], edges[m] + 1)) for m in range(k)],
                     dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Served mix: a stream of parameter-sweep requests of mixed model, size and
+# horizon.  Each request is a contiguous slice of one of the sweeps of the
+# first three workloads (RK4 Duffing, Cash-Karp Duffing, Keller-Miksis), with
+# its own horizon; arrival times are a Poisson process.
+# ---------------------------------------------------------------------------
+
+SERVED_MODELS = ("duffing_rk4", "duffing_rkck45", "keller_miksis")
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    problem: Problem
+    periods: int
+
+
+def _served_base(name: str) -> Problem:
+    if name == "duffing_rk4":
+        return duffing_rk4_sweep(1 << 16)
+    if name == "duffing_rkck45":
+        return duffing_rkck45_sweep(256, 256)
+    return keller_miksis_sweep(1 << 16)
+
+
+def served_mix(n_requests: int = 600, *, seed: int = 0, tol: float = 1e-7,
+               sizes=(256, 65536), periods=(8, 256)) -> list[Request]:
+    """Requests: model uniform over the three sweeps; size log-uniform over
+    ``sizes`` systems (a contiguous slice at a uniform offset); horizon
+    log-uniform over ``periods`` forcing periods, the last 1/16 (at least one)
+    recorded; adaptive requests at rtol = atol = ``tol``."""
+    g = np.random.default_rng(SEED_BASE + 100 + seed)
+    bases = {name: _served_base(name) for name in SERVED_MODELS}
+    out = []
+    for rid in range(n_requests):
+        name = SERVED_MODELS[int(g.integers(len(SERVED_MODELS)))]
+        base = bases[name]
+        m = int(round(10.0 ** g.uniform(math.log10(sizes[0]), math.log10(sizes[1]))))
+        m = max(1, min(m, base.n))
+        a = int(g.integers(0, base.n - m + 1))
+        P = int(round(10.0 ** g.uniform(math.log10(periods[0]), math.log10(periods[1]))))
+        T = 1.0 if base.model == "keller_miksis" else TWO_PI
+        pb = base.subset(np.arange(a, a + m))
+        pb = pb.with_horizon(P * T, t_record=(P - max(1, P // 16)) * T)
+        pb = with_tolerance(pb, tol)
+        pb.name = f"{name}#{rid}"
+        out.append(Request(rid, pb, P))
+    return out
+
+
+def poisson_arrivals(n: int, qps: float, *, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of rate ``qps``, from 0."""
+    g = np.random.default_rng(SEED_BASE + 200 + seed)
+    gaps = g.exponential(1.0 / qps, size=n)
+    return np.cumsum(gaps) - gaps[0]

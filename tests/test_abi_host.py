@@ -62,12 +62,13 @@ def test_model_dims(lib):
     assert E.model_dims("keller_miksis") == (2, 13)
     assert E.model_dims("relief_valve") == (3, 5)
     assert E.model_dims("ballistic") == (2, 1)
+    assert E.model_dims("duffing_lyapunov") == (4, 5)
     ns, np_ = C.c_int32(), C.c_int32()
     assert lib.ode_ensemble_model_dims(99, C.byref(ns), C.byref(np_)) == E.EINVAL
 
 
 @pytest.mark.parametrize("desc", [(99, 0, 0, 0), (1, 7, 0, 0), (1, 0, 5, 0), (1, 0, 0, 96),
-                                  (1, 0, 0, 512), (1, 0, 0, 32)])
+                                  (1, 0, 0, 512), (1, 0, 0, 32), (1, 0, 0, 0, -1)])
 def test_create_rejects_bad_descriptors_before_any_gpu_call(lib, desc):
     from paper_1810_03931_amd import ensemble as E
     d = E.Desc(*desc)
@@ -83,6 +84,9 @@ def test_null_arguments(lib):
     assert lib.ode_ensemble_create(None, None) == E.EINVAL
     a = E.SolveArgs()
     assert lib.ode_ensemble_solve(None, C.byref(a), None) == E.EINVAL
+    assert lib.ode_ensemble_solve_segments(None, C.byref(a), 1, 1.0, 1, None, None) == E.EINVAL
+    r = E.TuneResult()
+    assert lib.ode_ensemble_tune(None, C.byref(a), 1.0, None, C.byref(r)) == E.EINVAL
     assert lib.ode_ensemble_query(None, None) == E.EINVAL
     lib.ode_ensemble_destroy(None)  # NULL is ignored
 
@@ -95,11 +99,12 @@ def test_struct_layout_matches_c(tmp_path):
 #include <stdio.h>
 #include "ode_ensemble.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(ode_solve_args), sizeof(ode_event_spec),
-         sizeof(ode_accessory_spec), sizeof(ode_ensemble_desc), sizeof(ode_ensemble_info));
-  printf("%zu %zu %zu %zu %zu\\n", offsetof(ode_solve_args, rtol), offsetof(ode_solve_args, h0),
-         offsetof(ode_solve_args, max_steps), offsetof(ode_solve_args, events),
-         offsetof(ode_solve_args, accessory_specs));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ode_solve_args), sizeof(ode_event_spec),
+         sizeof(ode_accessory_spec), sizeof(ode_ensemble_desc), sizeof(ode_ensemble_info),
+         sizeof(ode_tune_result));
+  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(ode_solve_args, rtol), offsetof(ode_solve_args, h0),
+         offsetof(ode_solve_args, section_period), offsetof(ode_solve_args, max_steps),
+         offsetof(ode_solve_args, events), offsetof(ode_solve_args, accessory_specs));
   return 0;
 }
 """)
@@ -109,10 +114,10 @@ int main(void) {
     sizes, offs = [list(map(int, l.split())) for l in
                    subprocess.run([str(exe)], capture_output=True, text=True).stdout.splitlines()]
     assert sizes == [C.sizeof(E.SolveArgs), C.sizeof(E.EventSpec), C.sizeof(E.AccessorySpec),
-                     C.sizeof(E.Desc), C.sizeof(E.Info)]
+                     C.sizeof(E.Desc), C.sizeof(E.Info), C.sizeof(E.TuneResult)]
     S = E.SolveArgs
-    assert offs == [S.rtol.offset, S.h0.offset, S.max_steps.offset, S.events.offset,
-                    S.accessory_specs.offset]
+    assert offs == [S.rtol.offset, S.h0.offset, S.section_period.offset, S.max_steps.offset,
+                    S.events.offset, S.accessory_specs.offset]
 
 
 def _sources(d, exts):

@@ -224,3 +224,28 @@ def test_max_steps_budget(oracle):
     assert r["status"][0] == O.MAX_STEPS
     assert r["counts"][:, 0].sum() == 37
     assert 0.0 < td[0, 0] < 100.0
+
+
+def test_per_system_record_start_equals_separate_solves():
+    """A per-system window start gives, for every system, what a separate
+    solve with that scalar t_record gives (bit for bit)."""
+    from oracle import oracle as O
+    import numpy as np
+    n = 12
+    T = 2 * np.pi
+    k = np.linspace(0.1, 0.5, n)
+    p = np.stack([k, np.full(n, 1.0), np.ones(n), np.ones(n), np.ones(n)])
+    y0 = np.zeros((2, n))
+    td0 = np.stack([np.zeros(n), np.full(n, 6 * T)])
+    starts = np.linspace(-1.0, 7 * T, n)          # before t0, inside, and after t1
+    opts = dict(h0=1e-3, rtol=1e-9, atol=1e-9, accessories=[("max", 0), ("min", 1)],
+                events=[dict(component=1, direction=-1, record_component=0)], record_cap=8)
+    td, y = td0.copy(), y0.copy()
+    r = O.solve("duffing", "rkck45", td, y, p, record_start=starts, **opts)
+    for s in range(n):
+        tds, ys = td0[:, s:s + 1].copy(), y0[:, s:s + 1].copy()
+        rs = O.solve("duffing", "rkck45", tds, ys, p[:, s:s + 1].copy(), t_record=starts[s], **opts)
+        assert np.array_equal(ys[:, 0], y[:, s]) and tds[0, 0] == td[0, s]
+        np.testing.assert_array_equal(rs["acc"][:, 0], r["acc"][:, s])
+        np.testing.assert_array_equal(rs["event_counts"][:, 0], r["event_counts"][:, s])
+        np.testing.assert_array_equal(rs["event_records"][:, :, 0], r["event_records"][:, :, s])
