@@ -1,0 +1,250 @@
+"""Serving loop: continuous admission of parameter-sweep requests.
+
+Requests (``inputs.Request``: a sweep of systems with its model, method,
+horizon and options) arrive at given times.  The loop admits a waiting
+request as soon as a slot is free and the device-memory budget has room for
+its arrays.  A slot is a HIP stream with its own solver handles, so one
+handle never runs two solves at once.  On admission the loop copies the
+request's inputs to the device on the slot's stream and enqueues its solve.
+It polls completion events, copies the results back, releases the memory and
+admits the next requests.
+
+Waiting requests that can share a launch (same model, method and options;
+horizons within a factor of two) are batched into one solve: their systems
+sit side by side, each with its own window start (``record_start``).
+Launches on different slots run concurrently.  When one launch's workgroups
+retire, the freed compute units take workgroups of the others, so requests
+arriving while others run start right away, up to the slot and memory
+limits.  No system's arithmetic depends on its neighbours or on the launch
+shape, so a result is bit-identical alone and in the mix.
+
+Latency is measured from arrival to the results being on the host, p50/p99
+over the requests.  Throughput is the accepted steps of all requests divided
+by the time from the first arrival to the last completion.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import sys
+import time
+from collections import deque
+from typing import Optional
+
+import numpy as np
+
+from . import ensemble as E
+from . import inputs as I
+
+
+def request_bytes(pb: I.Problem) -> int:
+    """Device bytes a request holds while resident."""
+    n = pb.n
+    n_acc = len(pb.options.get("accessories", ()))
+    evs = pb.options.get("events", ())
+    cap = pb.options.get("record_cap", 0) if any(e.get("record_component", -1) >= 0
+                                                 for e in evs) else 0
+    rows = 2 + pb.state.shape[0] + pb.params.shape[0] + 2 * n_acc + 2 * cap
+    return n * (8 * rows + 4 + 3 * 8 + 4 * len(evs))
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    done: float
+    steps: int
+    outputs: dict
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def _batch_key(pb: I.Problem) -> str:
+    """Requests with equal keys can share one launch: same model, method and
+    options except the window start, which becomes per system."""
+    opts = {k: v for k, v in pb.options.items() if k != "t_record"}
+    return json.dumps([pb.model, pb.method, opts], sort_keys=True, default=str)
+
+
+class _Slot:
+    def __init__(self, torch, device, precision, block_size):
+        self.torch = torch
+        self.stream = torch.cuda.Stream(device=device)
+        self.device = device
+        self.precision = precision
+        self.block_size = block_size
+        self.handles = {}
+        self.busy = None
+
+    def handle(self, model, method):
+        key = (model, method)
+        if key not in self.handles:
+            self.handles[key] = E.Ensemble(model, method, precision=self.precision,
+                                           block_size=self.block_size)
+        return self.handles[key]
+
+    def launch(self, batch: list, nbytes: int, now: float):
+        """One solve for the requests of ``batch`` [(request, arrival)], their
+        systems side by side, each system with its request's window start."""
+        torch = self.torch
+        pbs = [req.problem for req, _ in batch]
+        first = pbs[0]
+        cat = lambda f: np.ascontiguousarray(np.concatenate([f(pb) for pb in pbs], axis=-1))
+        td = cat(lambda pb: pb.time_domain)
+        y = cat(lambda pb: pb.state)
+        p = cat(lambda pb: pb.params)
+        rec = cat(lambda pb: np.full(pb.n, pb.options.get("t_record", -np.inf)))
+        opts = {k: v for k, v in first.options.items() if k != "t_record"}
+        with torch.cuda.stream(self.stream):
+            hosts = [torch.from_numpy(a).pin_memory() for a in (td, y, p, rec)]
+            dev = [h.to(self.device, non_blocking=True) for h in hosts]
+            ens = self.handle(first.model, first.method)
+            out = ens.solve(dev[0], dev[1], dev[2], record_start=dev[3], stream=self.stream,
+                            **opts)
+            res = {"t": dev[0][0], "y": dev[1], "status": out["status"], "counts": out["counts"]}
+            if out.get("acc") is not None:
+                res["acc"] = out["acc"]
+            if out.get("event_counts") is not None:
+                res["event_counts"] = out["event_counts"]
+            host = {k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True)
+                    for k, v in res.items()}
+            for k, v in res.items():
+                host[k].copy_(v, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self.busy = (batch, now, nbytes, (hosts, dev, out, res), host, ev)
+
+
+class Server:
+    """Admits requests into ``slots`` concurrent streams within a device
+    memory budget of ``memory_budget`` bytes; waiting requests that can
+    share a launch are batched (up to ``max_batch_systems`` systems, horizons
+    within ``horizon_ratio`` of the oldest waiting request's)."""
+
+    def __init__(self, *, precision: str = "fp64", slots: int = 4,
+                 memory_budget: int = 8 << 30, block_size: int = 0, device: int = 0,
+                 max_batch_systems: int = 1 << 17, horizon_ratio: float = 2.0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.budget = int(memory_budget)
+        self.max_batch = int(max_batch_systems)
+        self.ratio = float(horizon_ratio)
+        self.slots = [_Slot(torch, self.device, precision, block_size) for _ in range(slots)]
+
+    def _take_batch(self, waiting: deque, free_bytes: int):
+        """The oldest waiting request and the later ones that can join it."""
+        span = lambda r: float(np.max(r.problem.time_domain[1] - r.problem.time_domain[0]))
+        head, arr = waiting.popleft()
+        key, h0 = _batch_key(head.problem), span(head)
+        batch = [(head, arr)]
+        size, nbytes = head.problem.n, request_bytes(head.problem)
+        keep = deque()
+        while waiting:
+            req, arr = waiting.popleft()
+            b = request_bytes(req.problem)
+            if (_batch_key(req.problem) == key and h0 / self.ratio <= span(req) <= h0 * self.ratio
+                    and size + req.problem.n <= self.max_batch and nbytes + b <= free_bytes):
+                batch.append((req, arr))
+                size += req.problem.n
+                nbytes += b
+            else:
+                keep.append((req, arr))
+        waiting.extend(keep)
+        return batch, nbytes
+
+    def run(self, requests: list, arrivals: Optional[np.ndarray] = None,
+            poll_s: float = 5e-5) -> list:
+        """Serve ``requests`` arriving at ``arrivals`` (seconds from the start;
+        None: all at once).  Returns one Result per request, in request
+        order."""
+        if arrivals is None:
+            arrivals = np.zeros(len(requests))
+        order = np.argsort(arrivals, kind="stable")
+        for r in requests:
+            if request_bytes(r.problem) > self.budget:
+                raise ValueError(f"request {r.rid} needs more than the memory budget")
+        waiting = deque()
+        future = deque((requests[i], float(arrivals[i])) for i in order)
+        results = {}
+        used = 0
+        t0 = time.perf_counter()
+        while future or waiting or any(s.busy for s in self.slots):
+            now = time.perf_counter() - t0
+            while future and future[0][1] <= now:
+                waiting.append(future.popleft())
+            # retire finished launches
+            for s in self.slots:
+                if s.busy and s.busy[-1].query():
+                    batch, adm, nbytes, _dev, host, _ev = s.busy
+                    done = time.perf_counter() - t0
+                    out = {k: v.numpy() for k, v in host.items()}
+                    lo = 0
+                    for req, arr in batch:
+                        hi = lo + req.problem.n
+                        part = {k: v[..., lo:hi] for k, v in out.items()}
+                        results[req.rid] = Result(req.rid, arr, adm, done,
+                                                  int(part["counts"][0].sum()), part)
+                        lo = hi
+                    used -= nbytes
+                    s.busy = None
+            # admit, oldest first, while a slot and memory are free
+            while waiting:
+                slot = next((s for s in self.slots if not s.busy), None)
+                if slot is None or used + request_bytes(waiting[0][0].problem) > self.budget:
+                    break
+                batch, nbytes = self._take_batch(waiting, self.budget - used)
+                used += nbytes
+                slot.launch(batch, nbytes, time.perf_counter() - t0)
+            if not waiting and future and not any(s.busy for s in self.slots):
+                time.sleep(max(0.0, min(future[0][1] - now, 1e-3)))
+            else:
+                time.sleep(poll_s)
+        return [results[r.rid] for r in requests]
+
+
+def summarize(results: list, label: str) -> dict:
+    lat = np.array([r.latency for r in results])
+    span = max(r.done for r in results) - min(r.arrival for r in results)
+    steps = sum(r.steps for r in results)
+    return {"mode": label, "requests": len(results),
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "system_steps_per_s": steps / span, "span_s": span, "accepted_steps": steps}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description="served mix: Poisson arrivals of sweep requests")
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8],
+                    help="offered load as fractions of the measured saturation rate")
+    ap.add_argument("--precision", nargs="+", default=["fp64", "mixed"])
+    ap.add_argument("--max-periods", type=int, default=256)
+    args = ap.parse_args(argv)
+    reqs = I.served_mix(args.requests, tol=args.tol, periods=(8, args.max_periods))
+    lines = []
+    for prec in args.precision:
+        srv = Server(precision=prec, slots=args.slots)
+        srv.run(reqs[: min(8, len(reqs))])                     # warm up handles and kernels
+        sat = summarize(srv.run(reqs), f"{prec}/saturation")   # all requests at once
+        sat_qps = len(reqs) / sat["span_s"]
+        sat["qps"] = sat_qps
+        lines.append(sat)
+        print(json.dumps(sat), flush=True)
+        for load in args.load:
+            arr = I.poisson_arrivals(len(reqs), load * sat_qps)
+            st = summarize(srv.run(reqs, arr), f"{prec}/load{load}")
+            st["qps"] = load * sat_qps
+            lines.append(st)
+            print(json.dumps(st), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

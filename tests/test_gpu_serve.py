@@ -1,0 +1,92 @@
+"""Serving loop: per-system window starts (what lets requests share a launch)
+against the oracle, results bit-identical alone and in the mix, and served
+results against the oracle."""
+import numpy as np
+import pytest
+
+from _parity import compare, oracle_with_floor, run_oracle
+from paper_1810_03931_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_mix(n=18, seed=3):
+    return I.served_mix(n, seed=seed, sizes=(64, 1500), periods=(2, 12))
+
+
+def test_record_start_matches_oracle(ode, oracle):
+    import torch
+    from oracle import oracle as O
+    from paper_1810_03931_amd import ensemble as E
+    pb = I.short_horizon(I.duffing_rkck45_sweep()).subset(np.arange(0, 1 << 17, 131))
+    pb.time_domain[1] = 3 * I.TWO_PI
+    starts = np.linspace(-1.0, 3.5 * I.TWO_PI, pb.n)
+    # the oracle with the same per-system starts
+    td, y = pb.time_domain.copy(), pb.state.copy()
+    o = O.solve(pb.model, pb.method, td, y, pb.params, record_start=starts, **pb.options)
+    o.update(y=y, t=td[0], t1=pb.time_domain[1])
+    dev = torch.device("cuda", 0)
+    tdg = torch.as_tensor(pb.time_domain, device=dev).clone()
+    yg = torch.as_tensor(pb.state, device=dev).clone()
+    pg = torch.as_tensor(pb.params, device=dev).clone()
+    ens = E.Ensemble(pb.model, pb.method)
+    out = ens.solve(tdg, yg, pg, record_start=torch.as_tensor(starts, device=dev), **pb.options)
+    torch.cuda.synchronize()
+    g = {"y": yg.cpu().numpy(), "t": tdg[0].cpu().numpy(), "status": out["status"].cpu().numpy(),
+         "counts": out["counts"].cpu().numpy(), "acc": np.zeros((0, pb.n)),
+         "event_counts": out["event_counts"].cpu().numpy(),
+         "event_records": out["event_records"].cpu().numpy()}
+    o["acc"] = np.zeros((0, pb.n))
+    st = compare(g, o, label="record_start")
+    print(f"[serve] per-system window start vs oracle: {st}", flush=True)
+
+
+def test_results_same_alone_and_in_mix(ode):
+    from paper_1810_03931_amd.serve import Server
+    for prec in ("fp64", "mixed"):
+        reqs = _small_mix()
+        alone = Server(precision=prec, slots=1, max_batch_systems=0)
+        ref = [alone.run([r])[0] for r in reqs]
+        srv = Server(precision=prec, slots=4)
+        arr = I.poisson_arrivals(len(reqs), 400.0, seed=1)
+        mixed = srv.run(reqs, arr)
+        batched = Server(precision=prec, slots=2).run(reqs)      # all at once: batches form
+        for a, b, c in zip(ref, mixed, batched):
+            for k in a.outputs:
+                assert np.array_equal(a.outputs[k], b.outputs[k], equal_nan=True), (prec, a.rid, k)
+                assert np.array_equal(a.outputs[k], c.outputs[k], equal_nan=True), (prec, a.rid, k)
+        lat = np.array([r.latency for r in mixed])
+        print(f"[serve] {prec}: {len(reqs)} requests identical alone, under Poisson arrivals and "
+              f"batched; latency p50 {np.median(lat) * 1e3:.1f} ms", flush=True)
+
+
+def test_served_results_match_oracle(ode, oracle):
+    from paper_1810_03931_amd.serve import Server
+    reqs = _small_mix(9, seed=4)
+    res = Server(precision="fp64", slots=3).run(reqs)
+    for req, r in zip(reqs, res):
+        pb = req.problem
+        o, floor, fragile = oracle_with_floor(pb)
+        g = dict(r.outputs)
+        g.setdefault("acc", np.zeros((0, pb.n)))
+        g.setdefault("event_counts", np.zeros((0, pb.n), dtype=np.int32))
+        g["event_records"] = np.zeros((0, 2, pb.n))
+        o = dict(o, event_records=np.zeros((0, 2, pb.n)))
+        # Keller-Miksis slices over up to 12 periods hold many systems the
+        # oracle's own twins cannot settle (fragile); they get the loose bar.
+        st = compare(g, o, floor=floor, fragile=fragile, label=pb.name, max_flip_frac=0.1)
+        print(f"[serve] {pb.name} n={pb.n} periods={req.periods}: {st}", flush=True)
+
+
+def test_memory_budget_limits_admission(ode):
+    from paper_1810_03931_amd.serve import Server, request_bytes
+    reqs = _small_mix(10, seed=5)
+    budget = max(request_bytes(r.problem) for r in reqs)
+    res = Server(precision="fp64", slots=4, memory_budget=budget).run(reqs)
+    # at every admission, the requests in flight fit the budget
+    for r in res:
+        inflight = sum(request_bytes(q.problem) for q, x in zip(reqs, res)
+                       if x.admitted <= r.admitted < x.done)
+        assert inflight <= budget
+    with pytest.raises(ValueError):
+        Server(precision="fp64", memory_budget=budget // 4).run(reqs)
