@@ -34,12 +34,9 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # every lane has the parameters of system S, so no lane is masked):
 #   FLOP = 64*(ADD + MUL + TRANS) + 128*FMA of SQ_INSTS_VALU_*_F64, / attempts.
 # The figure includes the FP64 work the math library does inside cos/sin/pow.
-# Source: profiles/<workload>_fp64_counters.txt ("uniform" block).  Workloads
-# without a calibration fall back to a count from the formulas (FMA = 2,
-# add/mul/div/sqrt = 1) plus 40 FLOP per library transcendental.
-FLOPS_PER_ATTEMPT = {
-    "duffing_rkck45": (466.7, "counter calibration, uniform lanes"),
-}
+# It is read from profiles/<workload>_fp64_counters.txt ("uniform" block).
+# Workloads without a calibration fall back to a count from the formulas
+# (FMA = 2, add/mul/div/sqrt = 1) plus 40 FLOP per library transcendental.
 FLOPS_ESTIMATE = {
     ("duffing", "rk4"): 70 + 4 * 40,
     ("duffing", "rkck45"): 191 + 7 * 40,
@@ -123,6 +120,28 @@ def kernel_source_hash():
             h.update(name.encode() + b"\0" + f.read())
     h.update(" ".join(build.FLAGS[:-4]).encode())
     return h.hexdigest()[:16]
+
+
+def calibrated_flops(workload):
+    """(FP64 FLOP per attempt, source) from the committed counter summary of
+    this workload's lock-step run, or None."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_fp64_counters.txt")
+    if not os.path.exists(path):
+        return None
+    block, val, src_hash = None, None, None
+    for line in open(path):
+        if line.startswith("# kernel sources hash"):
+            src_hash = line.split()[-1]
+        elif line.startswith("["):
+            block = line[1:line.index("]")]
+        elif block == "uniform" and "fp64_flop_per_attempt:" in line:
+            val = float(line.split(":", 1)[1])
+    if val is None:
+        return None
+    note = "counter calibration, uniform lanes"
+    if src_hash != kernel_source_hash():
+        note += " (taken on an earlier build of the kernel sources)"
+    return val, note
 
 
 def measured_traffic(workload):
@@ -220,9 +239,9 @@ def main():
     ms_per_step = total_ms / args.steps
     value = accepted / (ms_per_step / 1e3)
 
-    key = pb.name if (args.precision == "fp64" and args.tol <= 0) else None
-    flops_attempt, flops_src = FLOPS_PER_ATTEMPT.get(
-        key, (FLOPS_ESTIMATE[(pb.model, pb.method)], "estimate from the formulas"))
+    cal = calibrated_flops(pb.name) if (args.precision == "fp64" and args.tol <= 0) else None
+    flops_attempt, flops_src = cal or (FLOPS_ESTIMATE[(pb.model, pb.method)],
+                                       "estimate from the formulas")
     kern_s = float(kernel_ms.mean()) / 1e3
     achieved = attempts * flops_attempt / kern_s / 1e12
     info = ens.info()

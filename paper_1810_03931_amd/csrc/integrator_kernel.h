@@ -512,6 +512,11 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     }
     if (!active) continue;
 
+    // Launch constants are read through a fresh opaque kernel-argument pointer
+    // in every attempt: scalar loads at the point of use, instead of values
+    // held in scalar registers across the loop (which the transcendental
+    // routines' constants would push into vector-register lanes).
+    const ParamsRef kp = fresh_params();
     // ---- choose this attempt's step length ----
     double t_b = t1, h_att;
     bool clipped = false;
@@ -519,17 +524,17 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       h_att = sc;
     } else {
       t_b = (!window_open && t_rec < t1) ? t_rec : t1;
-      if (c.section_period > 0.0) {
-        const double t_sec = __dmul_rn(sec_n, c.section_period);
+      if (kp->c.section_period > 0.0) {
+        const double t_sec = __dmul_rn(sec_n, kp->c.section_period);
         t_b = (t_sec < t_b) ? t_sec : t_b;
       }
       if (METHOD == kMethodRK4) {
-        const double t_grid = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), c.h0));
-        if (t_grid >= __dsub_rn(t_b, __dmul_rn(1e-9, c.h0))) {
+        const double t_grid = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), kp->c.h0));
+        if (t_grid >= __dsub_rn(t_b, __dmul_rn(1e-9, kp->c.h0))) {
           h_att = t_b - t;
           clipped = true;
         } else {
-          h_att = c.h0;
+          h_att = kp->c.h0;
         }
       } else {
         h_att = h;
@@ -571,24 +576,24 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
           has_nan |= isnan(yn[i]);
-          const double sc_i = fma(c.rtol[i], fmax(fabs(y[i]), fabs(yn[i])), c.atol[i]);
+          const double sc_i = fma(kp->c.rtol[i], fmax(fabs(y[i]), fabs(yn[i])), kp->c.atol[i]);
           const double r = fabs(err[i]) / sc_i;
           has_nan |= isnan(r);
           E = (r > E) ? r : E;
         }
         if (has_nan) {
           passed = false;
-          if (h_att <= c.h_min) {
+          if (h_att <= kp->c.h_min) {
             status = kFailNan;
           } else {
-            h = fmax(c.h_min, c.shrink * h_att);
+            h = fmax(kp->c.h_min, kp->c.shrink * h_att);
             ++n_rej;
           }
         } else {
-          double fac = (E == 0.0) ? c.grow : 0.9 * inv_fifth_root(E);
-          fac = fmax(c.shrink, fmin(c.grow, fac));
-          h_next = fmax(c.h_min, fmin(c.h_max, fac * h_att));
-          if (!(E <= 1.0) && h_att > c.h_min) {
+          double fac = (E == 0.0) ? kp->c.grow : 0.9 * inv_fifth_root(E);
+          fac = fmax(kp->c.shrink, fmin(kp->c.grow, fac));
+          h_next = fmax(kp->c.h_min, fmin(kp->c.h_max, fac * h_att));
+          if (!(E <= 1.0) && h_att > kp->c.h_min) {
             passed = false;
             h = h_next;
             ++n_rej;
@@ -599,9 +604,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
         uint32_t cross = 0, land = 0;
 #pragma unroll
         for (int j = 0; j < NEV; ++j) {
-          if (j < c.n_events && !((leaving >> j) & 1u)) {
-            const double Fn = pick(yn, c.ev[j].component) - c.ev[j].level;
-            const int d = detect(F[j], Fn, c.ev[j].direction, c.ev[j].tolerance);
+          if (j < kp->c.n_events && !((leaving >> j) & 1u)) {
+            const double Fn = pick(yn, kp->c.ev[j].component) - kp->c.ev[j].level;
+            const int d = detect(F[j], Fn, kp->c.ev[j].direction, kp->c.ev[j].tolerance);
             cross |= (d == 1 ? 1u : 0u) << j;
             land |= (d == 2 ? 1u : 0u) << j;
           }
@@ -616,9 +621,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
           for (int j = 0; j < NEV; ++j)
             if (top == (1u << j)) {
-              loc_c = c.ev[j].component;
-              loc_level = c.ev[j].level;
-              loc_tol = c.ev[j].tolerance;
+              loc_c = kp->c.ev[j].component;
+              loc_level = kp->c.ev[j].level;
+              loc_tol = kp->c.ev[j].tolerance;
               ga = F[j];
             }
           gb = pick(yn, loc_c) - loc_level;
@@ -635,7 +640,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
           if (clipped)
             tn = t_b;
           else if (METHOD == kMethodRK4)
-            tn = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), c.h0));
+            tn = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), kp->c.h0));
           else
             tn = t + h_att;
           if (METHOD == kMethodRKCK45) {
@@ -660,9 +665,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
         det = loc_bit;
 #pragma unroll
         for (int j = 0; j < NEV; ++j) {
-          if (j < c.n_events && (1u << j) != loc_bit && !((leaving >> j) & 1u)) {
-            const double Fn = pick(yn, c.ev[j].component) - c.ev[j].level;
-            det |= (detect(F[j], Fn, c.ev[j].direction, c.ev[j].tolerance) != 0 ? 1u : 0u) << j;
+          if (j < kp->c.n_events && (1u << j) != loc_bit && !((leaving >> j) & 1u)) {
+            const double Fn = pick(yn, kp->c.ev[j].component) - kp->c.ev[j].level;
+            det |= (detect(F[j], Fn, kp->c.ev[j].direction, kp->c.ev[j].tolerance) != 0 ? 1u : 0u) << j;
           }
         }
       } else {
@@ -701,9 +706,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       } else {
 #pragma unroll
         for (int k = 0; k < NACC; ++k)
-          if (k < c.n_acc && c.acc[k].kind != kAccLogReset) {
-            const double v = pick(y, c.acc[k].component);
-            const bool better = (c.acc[k].kind == kAccMax) ? (v > accv[k]) : (v < accv[k]);
+          if (k < kp->c.n_acc && kp->c.acc[k].kind != kAccLogReset) {
+            const double v = pick(y, kp->c.acc[k].component);
+            const bool better = (kp->c.acc[k].kind == kAccMax) ? (v > accv[k]) : (v < accv[k]);
             accv[k] = better ? v : accv[k];
             acct[k] = better ? t : acct[k];
           }
@@ -739,11 +744,11 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       // Poincare section reached (the step was clipped to it): the Lyapunov
       // accumulators add ln y[c] for sections after the window start, and
       // y[c] restarts from 1 at every section (paper Sec. 2.1)
-      if (c.section_period > 0.0 && t == __dmul_rn(sec_n, c.section_period)) {
+      if (kp->c.section_period > 0.0 && t == __dmul_rn(sec_n, kp->c.section_period)) {
 #pragma unroll
         for (int k = 0; k < NACC; ++k)
-          if (k < c.n_acc && c.acc[k].kind == kAccLogReset) {
-            const int comp = c.acc[k].component;
+          if (k < kp->c.n_acc && kp->c.acc[k].kind == kAccLogReset) {
+            const int comp = kp->c.acc[k].component;
             if (window_open && t > t_rec) {
               accv[k] = accv[k] + log(pick(y, comp));
               acct[k] = acct[k] + 1.0;
@@ -756,16 +761,16 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       // that stay inside after a detection count towards the equilibrium stop
 #pragma unroll
       for (int j = 0; j < NEV; ++j) {
-        if (j < c.n_events) {
-          F[j] = pick(y, c.ev[j].component) - c.ev[j].level;
-          const bool inside = fabs(F[j]) <= c.ev[j].tolerance;
+        if (j < kp->c.n_events) {
+          F[j] = pick(y, kp->c.ev[j].component) - kp->c.ev[j].level;
+          const bool inside = fabs(F[j]) <= kp->c.ev[j].tolerance;
           const uint32_t bit = 1u << j;
           if (((det | ~leaving) & bit) != 0) {
             leaving = inside ? (leaving | bit) : (leaving & ~bit);
             zone[j] = 0;
           } else if (inside) {
             ++zone[j];
-            if (c.max_eq > 0 && zone[j] >= c.max_eq && status == kRunning)
+            if (kp->c.max_eq > 0 && zone[j] >= kp->c.max_eq && status == kRunning)
               status = kStopEquilibrium;
           } else {
             leaving &= ~bit;
@@ -775,7 +780,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       }
       if (status == kRunning && t >= t1) status = kDone;
     }
-    if (status == kRunning && !locating && attempts >= c.max_steps) status = kMaxSteps;
+    if (status == kRunning && !locating && attempts >= kp->c.max_steps) status = kMaxSteps;
     if (status != kRunning) retire();
   }
 

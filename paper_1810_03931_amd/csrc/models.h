@@ -43,6 +43,28 @@ __device__ __forceinline__ void rotate(double delta, double sb, double cb, doubl
   c = fma(cb, cm1, fma(-sb, sd, cb));
 }
 
+// The same rotation for |delta| <= 1/16 (steps short against the forcing
+// period, the usual case): Taylor through delta^9 / delta^10, truncation
+// below 2e-21.
+constexpr double kShortRotate = 0.0625;
+__device__ __forceinline__ void rotate_short(double delta, double sb, double cb, double &s,
+                                             double &c) {
+  const double d2 = delta * delta;
+  double ps = 1.0 / 362880.0;                //  1/9!
+  ps = fma(ps, d2, -1.0 / 5040.0);           // -1/7!
+  ps = fma(ps, d2, 1.0 / 120.0);             //  1/5!
+  ps = fma(ps, d2, -1.0 / 6.0);              // -1/3!
+  const double sd = fma(delta * d2, ps, delta);
+  double pc = -1.0 / 3628800.0;              // -1/10!
+  pc = fma(pc, d2, 1.0 / 40320.0);           //  1/8!
+  pc = fma(pc, d2, -1.0 / 720.0);            // -1/6!
+  pc = fma(pc, d2, 1.0 / 24.0);              //  1/4!
+  pc = fma(pc, d2, -0.5);                    // -1/2!
+  const double cm1 = d2 * pc;
+  s = fma(cb, sd, fma(sb, cm1, sb));
+  c = fma(cb, cm1, fma(-sb, sd, cb));
+}
+
 // sin/cos of `arg` given sin/cos of a nearby `base`.  The difference
 // arg - base is exact when the two are within a factor of two (Sterbenz), so
 // the function is evaluated at exactly `arg`; far from `base` (a long step)
@@ -55,6 +77,30 @@ __device__ __forceinline__ void sincos_near(double arg, double base, double sb, 
     rotate(delta, sb, cb, s, c);
   } else {
     sincos(arg, &s, &c);
+  }
+}
+
+// sin/cos of the stage phases arg[1..S-1] from those of arg[0] = base.  When
+// every stage lies within 1/16 of the base (one decision per attempt, so the
+// lanes of a wave normally agree) the short rotation serves all stages.
+template <int S>
+__device__ __forceinline__ void stage_sincos(const double (&arg)[S], double sb, double cb,
+                                             double (&s)[S], double (&c)[S]) {
+  double d[S];
+  double dmax = 0.0;
+#pragma unroll
+  for (int k = 1; k < S; ++k) {
+    d[k] = __dsub_rn(arg[k], arg[0]);
+    dmax = fmax(dmax, fabs(d[k]));
+  }
+  s[0] = sb;
+  c[0] = cb;
+  if (dmax <= kShortRotate) {
+#pragma unroll
+    for (int k = 1; k < S; ++k) rotate_short(d[k], sb, cb, s[k], c[k]);
+  } else {
+#pragma unroll
+    for (int k = 1; k < S; ++k) sincos_near(arg[k], arg[0], sb, cb, s[k], c[k]);
   }
 }
 
@@ -115,16 +161,14 @@ struct Duffing {
   template <int S>
   __device__ __forceinline__ static void forcing(const double (&ts)[S], const double (&p)[NP],
                                                  double (&F)[S][NF]) {
-    const double base = p[2] * ts[0];
-    double sb, cb;
-    sincos(base, &sb, &cb);
-    F[0][0] = cb;
+    double arg[S], sn[S], cs[S];
 #pragma unroll
-    for (int k = 1; k < S; ++k) {
-      double s, c;
-      sincos_near(__dmul_rn(p[2], ts[k]), base, sb, cb, s, c);
-      F[k][0] = c;
-    }
+    for (int k = 0; k < S; ++k) arg[k] = __dmul_rn(p[2], ts[k]);
+    double sb, cb;
+    sincos(arg[0], &sb, &cb);
+    stage_sincos<S>(arg, sb, cb, sn, cs);
+#pragma unroll
+    for (int k = 0; k < S; ++k) F[k][0] = cs[k];
   }
   __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&p)[NP],
                                              const double (&F)[NF], double (&f)[NS]) {
@@ -226,19 +270,23 @@ struct KellerMiksis {
                                                  double (&F)[S][NF]) {
     constexpr double kTwoPi = 6.283185307179586476925286766559;
     const double w2 = __dmul_rn(kTwoPi, C[11]);
-    const double b1 = kTwoPi * ts[0];
-    const double b2 = __dadd_rn(__dmul_rn(w2, ts[0]), C[12]);
-    double s1b, c1b, s2b, c2b;
-    sincos(b1, &s1b, &c1b);
-    sincos(b2, &s2b, &c2b);
-    F[0][0] = s1b;
-    F[0][1] = c1b;
-    F[0][2] = s2b;
-    F[0][3] = c2b;
+    double a1[S], a2[S], s1[S], c1[S], s2[S], c2[S];
 #pragma unroll
-    for (int k = 1; k < S; ++k) {
-      sincos_near(__dmul_rn(kTwoPi, ts[k]), b1, s1b, c1b, F[k][0], F[k][1]);
-      sincos_near(__dadd_rn(__dmul_rn(w2, ts[k]), C[12]), b2, s2b, c2b, F[k][2], F[k][3]);
+    for (int k = 0; k < S; ++k) {
+      a1[k] = __dmul_rn(kTwoPi, ts[k]);
+      a2[k] = __dadd_rn(__dmul_rn(w2, ts[k]), C[12]);
+    }
+    double s1b, c1b, s2b, c2b;
+    sincos(a1[0], &s1b, &c1b);
+    sincos(a2[0], &s2b, &c2b);
+    stage_sincos<S>(a1, s1b, c1b, s1, c1);
+    stage_sincos<S>(a2, s2b, c2b, s2, c2);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      F[k][0] = s1[k];
+      F[k][1] = c1[k];
+      F[k][2] = s2[k];
+      F[k][3] = c2[k];
     }
   }
   __device__ __forceinline__ static void rhs(const double (&y)[NS], const double (&C)[NP],
