@@ -109,13 +109,27 @@ def cpu_baseline(pb, target_s):
                       f"in {dt:.1f} s"}
 
 
-def kernel_source_hash():
-    """Hash of the integrator's sources: counter readings taken for another
-    version of the kernel are not reported."""
+# Sources that make up each workload's integrator kernel (besides the common
+# ones): counter summaries stay valid while these are unchanged.
+COMMON_SOURCES = ("integrator.h", "integrator_kernel.h", "model_common.h", "api.cpp")
+MODEL_SOURCES = {
+    "duffing": ("model_duffing.h", "kernels_duffing.hip"),
+    "keller_miksis": ("model_keller_miksis.h", "kernels_keller_miksis.hip"),
+    "relief_valve": ("model_relief_valve.h", "kernels_relief_valve.hip"),
+    "duffing_lyapunov": ("model_duffing.h", "model_duffing_lyapunov.h",
+                         "kernels_duffing_lyapunov.hip"),
+}
+
+
+def kernel_source_hash(workload="duffing_rkck45"):
+    """Hash of the sources of one workload's integrator kernel and the build
+    flags: counter readings taken for another version of that kernel are not
+    reported."""
     import hashlib
     from paper_1810_03931_amd import build
+    model = I.CONFIGS[workload]().model if workload in I.CONFIGS else workload
     h = hashlib.sha256()
-    for name in sorted(os.listdir(build.CSRC)):
+    for name in COMMON_SOURCES + MODEL_SOURCES[model]:
         with open(os.path.join(build.CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     h.update(" ".join(build.FLAGS[:-4]).encode())
@@ -139,7 +153,7 @@ def calibrated_flops(workload):
     if val is None:
         return None
     note = "counter calibration, uniform lanes"
-    if src_hash != kernel_source_hash():
+    if src_hash != kernel_source_hash(workload):
         note += " (taken on an earlier build of the kernel sources)"
     return val, note
 
@@ -155,7 +169,7 @@ def measured_traffic(workload):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != kernel_source_hash():
+    if vals.get("kernel_source_hash") != kernel_source_hash(workload):
         return None
     return float(vals["bytes_per_launch"])
 
@@ -166,7 +180,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.source_hash:
-        print(kernel_source_hash())
+        print(kernel_source_hash(args.config))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the systems are independent and this build "

@@ -18,7 +18,7 @@
 #pragma once
 
 #include "integrator.h"
-#include "models.h"
+#include "model_common.h"
 
 namespace odeens {
 

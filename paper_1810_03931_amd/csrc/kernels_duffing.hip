@@ -1,6 +1,7 @@
 // Integrator kernels specialised for the Duffing model (one translation unit
 // per model so the instantiations compile in parallel).
 #include "integrator_kernel.h"
+#include "model_duffing.h"
 
 namespace odeens {
 

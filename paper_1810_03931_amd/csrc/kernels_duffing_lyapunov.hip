@@ -2,6 +2,7 @@
 // linearisation (Lyapunov exponents); one translation unit per model so the
 // instantiations compile in parallel.
 #include "integrator_kernel.h"
+#include "model_duffing_lyapunov.h"
 
 namespace odeens {
 

@@ -1,6 +1,7 @@
 // Integrator kernels specialised for the ReliefValve model (one translation unit
 // per model so the instantiations compile in parallel).
 #include "integrator_kernel.h"
+#include "model_relief_valve.h"
 
 namespace odeens {
 
