@@ -141,3 +141,33 @@ def test_segments_arguments_are_validated(ode):
         assert ei.value.code == E.EINVAL
     torch.cuda.synchronize()
     assert torch.equal(td.cpu(), torch.as_tensor(pb.time_domain))
+
+
+def test_segments_with_gather_list_and_window_starts(ode):
+    """The graph honours a gather list (only the listed systems move) and
+    per-system window starts, exactly as the host loop does."""
+    import torch
+    from paper_1810_03931_amd import ensemble as E
+    pb = _duffing1(2000)
+    dev = torch.device("cuda", 0)
+    idx = torch.arange(3, 2000, 3, dtype=torch.int64, device=dev)
+    starts = torch.as_tensor(np.linspace(-1.0, 3 * T, pb.n), device=dev)
+    n_seg, first = 5, 2
+    ens = E.Ensemble(pb.model, pb.method)
+    td_e, y_e, p = _device(pb)
+    snaps_e = []
+    for k in range(n_seg):
+        td_e[1, idx] = td_e[0, idx] + T
+        out = ens.solve(td_e, y_e, p, system_index=idx, record_start=starts, **pb.options)
+        if k >= first:
+            snaps_e.append(torch.cat([y_e, out["acc"]])[:, idx].clone())
+    td, y, p = _device(pb)
+    out = ens.outputs(pb.n, n_accessories=1)
+    r = ens.solve_segments(td, y, p, n_seg, T, first_snapshot=first, system_index=idx,
+                           record_start=starts, out=out, **pb.options)
+    torch.cuda.synchronize()
+    assert torch.equal(td, td_e) and torch.equal(y, y_e)
+    assert torch.equal(r["snapshots"][:, :, idx], torch.stack(snaps_e))
+    untouched = torch.ones(pb.n, dtype=torch.bool, device=dev)
+    untouched[idx] = False
+    assert torch.equal(y[:, untouched].cpu(), torch.as_tensor(pb.state)[:, untouched.cpu()])

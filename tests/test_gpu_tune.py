@@ -33,3 +33,20 @@ def test_tune_reads_only_and_keeps_results(ode, name):
     plain = run_gpu(pb)
     for k in ("status", "counts", "y", "t", "acc", "event_counts", "event_records"):
         assert np.array_equal(tuned[k], plain[k], equal_nan=True), k
+
+
+def test_tune_with_gather_list_reads_only(ode):
+    import torch
+    from paper_1810_03931_amd import ensemble as E
+    pb = I.short_horizon(I.duffing_rkck45_sweep())
+    dev = torch.device("cuda", 0)
+    td = torch.as_tensor(pb.time_domain, device=dev).clone()
+    y = torch.as_tensor(pb.state, device=dev).clone()
+    p = torch.as_tensor(pb.params, device=dev).clone()
+    idx = torch.arange(0, pb.n, 5, dtype=torch.int64, device=dev)
+    ens = E.Ensemble(pb.model, pb.method)
+    r = ens.tune(td, y, p, probe_fraction=0.25, system_index=idx, **pb.options)
+    torch.cuda.synchronize()
+    assert torch.equal(td.cpu(), torch.as_tensor(pb.time_domain))
+    assert torch.equal(y.cpu(), torch.as_tensor(pb.state))
+    assert r["candidates"] >= 5 and r["best_ms"] <= r["default_ms"]
