@@ -58,6 +58,9 @@ def parse():
                     help="cap on resident workgroups per compute unit (0: all that fit)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the launch configuration (untimed) before the warmup")
+    ap.add_argument("--eager", action="store_true",
+                    help="repeated-horizon workloads: time the host loop of solve calls "
+                         "instead of the recorded graph")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=0.0,
                     help="override rtol = atol of the sweep (0: the sweep's own)")
@@ -219,13 +222,37 @@ def main():
         tuned = ens.tune(td0, y0, p, probe_fraction=0.25, stream=stream, **pb.options)
         print(f"tuned launch configuration: {tuned}", file=sys.stderr, flush=True)
 
+    segments = getattr(pb, "segments", None)
+    snaps = None
+    if segments is not None:
+        n_seg, seg_len, first = segments
+        snaps = torch.empty((n_seg - first, pb.state.shape[0] + 2 * len(pb.options["accessories"]),
+                             pb.n), dtype=torch.float64, device=dev)
+
+    def run_segments():
+        """The paper's loop of solves, one period each: one recorded graph, or
+        (--eager) the same loop of launches from the host."""
+        if not args.eager:
+            ens.solve_segments(td, y, p, n_seg, seg_len, first_snapshot=first, snapshots=snaps,
+                               out=out, stream=stream, **pb.options)
+            return
+        for k in range(n_seg):
+            td[1] = td[0] + seg_len
+            ens.solve(td, y, p, out=out, stream=stream, **pb.options)
+            if k >= first:
+                snaps[k - first, :2].copy_(y)
+                snaps[k - first, 2:].copy_(out["acc"])
+
     def step():
         td.copy_(td0)
         y.copy_(y0)
         k0 = torch.cuda.Event(enable_timing=True)
         k1 = torch.cuda.Event(enable_timing=True)
         k0.record(stream)
-        ens.solve(td, y, p, out=out, stream=stream, **pb.options)
+        if segments is None:
+            ens.solve(td, y, p, out=out, stream=stream, **pb.options)
+        else:
+            run_segments()
         k1.record(stream)
         return k0, k1
 
@@ -248,12 +275,19 @@ def main():
 
     per_system = out["counts"].sum(dim=0).cpu().numpy()     # attempts of each system
     counts = out["counts"].sum(dim=1).cpu().numpy()        # accepted, rejected, location
+    if segments is not None:
+        # the counts describe the last segment; RK4 takes the same number of
+        # steps in every period
+        per_system = per_system * n_seg
+        counts = counts * n_seg
     status = np.bincount(out["status"].cpu().numpy() & 0xFF, minlength=6)
     accepted, attempts = int(counts[0]), int(counts.sum())
     ms_per_step = total_ms / args.steps
     value = accepted / (ms_per_step / 1e3)
 
-    cal = calibrated_flops(pb.name) if (args.precision == "fp64" and args.tol <= 0) else None
+    # the repeated-horizon workload runs the RK4 Duffing kernel of duffing_rk4
+    cal_name = "duffing_rk4" if pb.name == "duffing_poincare" else pb.name
+    cal = calibrated_flops(cal_name) if (args.precision == "fp64" and args.tol <= 0) else None
     flops_attempt, flops_src = cal or (FLOPS_ESTIMATE[(pb.model, pb.method)],
                                        "estimate from the formulas")
     kern_s = float(kernel_ms.mean()) / 1e3
@@ -267,10 +301,13 @@ def main():
         "data": "synthetic (seeded parameter sweep)",
         "config": {"workload": pb.name + ("/uniform" if args.uniform >= 0 else ""),
                    "systems": pb.n, "equation": pb.model, "method": pb.method,
-                   "horizon": float(pb.time_domain[1, 0]), "t_record": pb.options.get("t_record"),
+                   "horizon": float(pb.time_domain[1, 0]) * (n_seg if segments else 1),
+                   "t_record": pb.options.get("t_record"),
                    "rtol": pb.options.get("rtol"), "precision": args.precision,
                    "block_size": info["block_size"], "blocks_per_cu": info["blocks_per_cu"],
-                   "resident_systems": info["resident_systems"], "tuned": tuned is not None},
+                   "resident_systems": info["resident_systems"], "tuned": tuned is not None,
+                   **({"segments": n_seg, "launch": "host loop" if args.eager else "HIP graph"}
+                      if segments is not None else {})},
         "attempted_steps_per_s": attempts / (ms_per_step / 1e3),
         "reject_frac": float(counts[1] / attempts), "location_frac": float(counts[2] / attempts),
         "status_counts": status.tolist(),

@@ -179,6 +179,28 @@ def duffing_lyapunov_sweep(n: int = 61440) -> Problem:
     return Problem("duffing_lyapunov", "duffing_lyapunov", "rkck45", td, state, params, opts)
 
 
+def duffing_poincare_sweep(n: int = 30720) -> Problem:
+    """The paper's Duffing1/Duffing2 workflow (Sec. 7.1): the double-well
+    Duffing oscillator (lin = -1, cub = 1, B = 0.3, omega = 1), k uniform over
+    [0.2, 0.3], RK4 with the paper's fixed step 1e-2, advanced one excitation
+    period per solve; 1024 transient + 32 kept periods, each kept period
+    storing the Poincare point (y1, y2) and the maximum of y1 in the period.
+
+    ``time_domain`` spans one period; ``segments`` = (periods, period,
+    first kept period)."""
+    g = _rng(6)
+    i = np.arange(n, dtype=np.float64)
+    k = 0.2 + 0.1 * i / max(n - 1, 1)
+    params = np.stack([k, np.full(n, 0.3), np.ones(n), np.full(n, -1.0), np.ones(n)])
+    state = g.uniform(-1e-3, 1e-3, size=(2, n))
+    T = TWO_PI
+    td = np.stack([np.zeros(n), np.full(n, T)])
+    opts = dict(h0=1e-2, accessories=[("max", 0)], max_steps=10**6)
+    pb = Problem("duffing_poincare", "duffing", "rk4", td, state, params, opts)
+    pb.segments = (1056, T, 1024)  # type: ignore[attr-defined]
+    return pb
+
+
 def keller_miksis_sweep(n: int = 1 << 18, *, cluster: bool = True) -> Problem:
     """Dual-frequency Keller-Miksis bubble, Cash-Karp at rtol = atol = 1e-10.
 
@@ -238,6 +260,7 @@ CONFIGS = {
     "keller_miksis": keller_miksis_sweep,
     "relief_valve": relief_valve_sweep,
     "duffing_lyapunov": duffing_lyapunov_sweep,
+    "duffing_poincare": duffing_poincare_sweep,
 }
 
 
