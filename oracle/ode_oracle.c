@@ -19,9 +19,11 @@
  * Readings of points the paper leaves open are marked READING below; every one
  * is listed in the design notes.
  *
- * Arithmetic: binary64, no contraction, glibc libm.  Parity unpinned parts:
- * the step-size controller formula (READING R3/R4) has no closed form; it is
- * pinned only through invariants (tolerance scaling, library cross-check).
+ * Arithmetic: binary64, no contraction, glibc libm.  The step-size
+ * controller (READING R3/R4) is a reading of the paper, not a closed form; its
+ * implementation is pinned against an independent matrix-polynomial
+ * formulation of the same method on linear systems (exact step counts), and
+ * through invariants (tolerance scaling, library cross-check).
  */
 #include "oracle.h"
 
