@@ -107,7 +107,14 @@ def cpu_baseline(pb, target_s):
             break
         k = int(min(pb.n, max(2 * k, k * target_s / max(dt, 1e-3))))
     acc = int(r["counts"][0].sum())
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": acc / dt, "unit": "system-steps/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu,
             "sample": f"{k} of {pb.n} systems (stratified), full horizon, {acc} accepted steps "
                       f"in {dt:.1f} s"}
 
@@ -122,6 +129,24 @@ MODEL_SOURCES = {
     "duffing_lyapunov": ("model_duffing.h", "model_duffing_lyapunov.h",
                          "kernels_duffing_lyapunov.hip"),
 }
+
+
+def device_facts(torch, info):
+    """Name, compute units and peak clock of the device (the FP64 peak is
+    CUs x clock x 128 FLOP/clk)."""
+    import ctypes
+    clock_khz = 0
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        v = ctypes.c_int(0)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), 5, 0) == 0:   # hipDeviceAttributeClockRate
+            clock_khz = v.value
+    except OSError:
+        pass
+    cus = int(info["compute_units"])
+    return {"name": torch.cuda.get_device_name(0), "compute_units": cus,
+            "peak_clock_mhz": clock_khz / 1e3,
+            "fp64_peak_tflops_from_clock": cus * clock_khz * 1e3 * 128 / 1e12 if clock_khz else None}
 
 
 def kernel_source_hash(workload="duffing_rkck45"):
@@ -292,6 +317,8 @@ def main():
                                        "estimate from the formulas")
     kern_s = float(kernel_ms.mean()) / 1e3
     achieved = attempts * flops_attempt / kern_s / 1e12
+    traffic = measured_traffic(pb.name) if (args.uniform < 0 and args.precision == "fp64"
+                                            and args.tol <= 0) else None
     info = ens.info()
     line = {
         "metric": METRIC, "value": value, "unit": "system-steps/s", "n_gpus": 1,
@@ -317,9 +344,12 @@ def main():
         "p50_ms": float(np.percentile(np.array(wall) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
         "kernel_ms": float(kernel_ms.mean()),
+        "device": device_facts(torch, info),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic(pb.name) if args.uniform < 0 else None,
+                     "traffic": traffic,
+                     "hbm_gb_s": traffic / kern_s / 1e9 if traffic else None,
+                     "hbm_frac_of_8_tb_s": traffic / kern_s / 8e12 if traffic else None,
                      "flops_per_attempt": flops_attempt, "flops_per_attempt_source": flops_src,
                      "attempts_per_launch": attempts},
     }
