@@ -160,6 +160,9 @@ def kernel_source_hash(workload="duffing_rkck45"):
     for name in COMMON_SOURCES + MODEL_SOURCES[model]:
         with open(os.path.join(build.CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
+        extra = getattr(build, "TU_FLAGS", {}).get(name)
+        if extra:
+            h.update(" ".join(extra).encode())
     h.update(" ".join(build.FLAGS[:-4]).encode())
     return h.hexdigest()[:16]
 
