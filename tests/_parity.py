@@ -1,7 +1,7 @@
 """Shared helpers of the GPU parity tests: run the oracle and the HIP path on
 the same seeded inputs and compare element by element.
 
-Tolerance (floating point): the spec bar is 1e-11 relative on final
+Tolerance (floating point): the target bar is 1e-11 relative on final
 states over short horizons.  "Relative" is taken per system against the size
 of its state, |a_i - b_i| <= rel * max(|b_i|, max_j |b_j|, tiny): components
 that pass through zero (a velocity at a turning point) are judged against
