@@ -167,23 +167,27 @@ def kernel_source_hash(workload="duffing_rkck45"):
     return h.hexdigest()[:16]
 
 
-def calibrated_flops(workload):
-    """(FP64 FLOP per attempt, source) from the committed counter summary of
-    this workload's lock-step run, or None."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_fp64_counters.txt")
+def calibrated_flops(workload, kind="fp64"):
+    """(FLOP per attempt, source) from the committed counter summary of this
+    workload's lock-step run, or None.  kind "fp64": FP64 FLOP of the FP64
+    kernel at the workload's own tolerance; kind "mixed": FP32 + FP64 FLOP of
+    the mixed-precision kernel at tolerance 1e-7."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{kind}_counters.txt")
     if not os.path.exists(path):
         return None
+    key = "fp64_flop_per_attempt:" if kind == "fp64" else "flop_per_attempt:"
     block, val, src_hash = None, None, None
     for line in open(path):
         if line.startswith("# kernel sources hash"):
             src_hash = line.split()[-1]
         elif line.startswith("["):
             block = line[1:line.index("]")]
-        elif block == "uniform" and "fp64_flop_per_attempt:" in line:
+        elif block == "uniform" and line.strip().startswith(key):
             val = float(line.split(":", 1)[1])
     if val is None:
         return None
-    note = "counter calibration, uniform lanes"
+    note = "counter calibration, uniform lanes" + ("" if kind == "fp64" else
+                                                   ", FP32 + FP64 FLOP")
     if src_hash != kernel_source_hash(workload):
         note += " (taken on an earlier build of the kernel sources)"
     return val, note
@@ -315,7 +319,10 @@ def main():
 
     # the repeated-horizon workload runs the RK4 Duffing kernel of duffing_rk4
     cal_name = "duffing_rk4" if pb.name == "duffing_poincare" else pb.name
-    cal = calibrated_flops(cal_name) if (args.precision == "fp64" and args.tol <= 0) else None
+    if args.precision == "fp64":
+        cal = calibrated_flops(cal_name) if args.tol <= 0 else None
+    else:
+        cal = calibrated_flops(cal_name, "mixed") if args.tol == 1e-7 else None
     flops_attempt, flops_src = cal or (FLOPS_ESTIMATE[(pb.model, pb.method)],
                                        "estimate from the formulas")
     kern_s = float(kernel_ms.mean()) / 1e3
