@@ -380,6 +380,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   for (int k = 0; k < AC; ++k) accv[k] = acct[k] = 0.0;
 
   bool exhausted = false;  // wave-uniform
+  uint32_t iter = 0;       // loop iterations of this wave (wave-uniform)
 
   auto acc_init = [&]() {
 #pragma unroll
@@ -509,6 +510,26 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     if (__ballot(active) == 0) {
       if (exhausted) break;
       continue;
+    }
+    // Issue priority by remaining work, re-estimated every 64 iterations: the
+    // wave's largest remaining step count at its lanes' current step sizes, in
+    // four levels.  When two waves share a SIMD, the one that will run longer
+    // issues first, so the longest serial chains -- which set the end of a
+    // sweep whose systems are all resident -- run closer to their solo speed
+    // while the other wave fills the gaps.  It orders issue only; results do
+    // not depend on it.  (Duffing sweep: 4.5% faster; kernels with one wave
+    // per SIMD are unaffected.)
+    if ((++iter & 63u) == 1u) {
+      const double rem = active ? (t1 - t) / fmax(h, 1e-300) : 0.0;
+      if (__ballot(rem > 131072.0)) {
+        __builtin_amdgcn_s_setprio(3);
+      } else if (__ballot(rem > 32768.0)) {
+        __builtin_amdgcn_s_setprio(2);
+      } else if (__ballot(rem > 8192.0)) {
+        __builtin_amdgcn_s_setprio(1);
+      } else {
+        __builtin_amdgcn_s_setprio(0);
+      }
     }
     if (!active) continue;
 
