@@ -333,6 +333,66 @@ __device__ __forceinline__ EventCtl event_of(ParamsRef q, int j) {
   return e;
 }
 
+// The launch constants that every attempt reads, held in vector registers
+// for the whole launch.  Each is read once before the attempt loop and passed
+// through an empty asm with a vector-register operand, so it stays in a VGPR
+// as a per-lane value instead of being re-read by a scalar load where it is
+// used.  Read through the kernel-argument pointer in the loop, an attempt
+// waits on about ten scalar-cache round trips, a third of the time of a wave
+// that runs alone on its SIMD (the slowest systems at the end of a sweep).
+template <int N, int EV, int AC>
+struct HotControl {
+  double rtol[N], atol[N];
+  double h0, h_min, h_max, grow, shrink, section_period;
+  double ev_level[EV], ev_tol[EV];
+  int32_t ev_comp[EV], ev_dir[EV];
+  int32_t acc_kind[AC], acc_comp[AC];
+  int32_t n_events, n_acc, max_eq, max_steps;
+};
+
+__device__ __forceinline__ double in_vgpr(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+__device__ __forceinline__ int32_t in_vgpr(int32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <int N, int EV, int AC>
+__device__ __forceinline__ HotControl<N, EV, AC> hot_control(const Control &c) {
+  static_assert(EV <= kMaxEvents && AC <= kMaxAcc && N <= kMaxState, "slot counts");
+  HotControl<N, EV, AC> h;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    h.rtol[i] = in_vgpr(c.rtol[i]);
+    h.atol[i] = in_vgpr(c.atol[i]);
+  }
+  h.h0 = in_vgpr(c.h0);
+  h.h_min = in_vgpr(c.h_min);
+  h.h_max = in_vgpr(c.h_max);
+  h.grow = in_vgpr(c.grow);
+  h.shrink = in_vgpr(c.shrink);
+  h.section_period = in_vgpr(c.section_period);
+#pragma unroll
+  for (int j = 0; j < EV; ++j) {
+    h.ev_level[j] = in_vgpr(c.ev[j].level);
+    h.ev_tol[j] = in_vgpr(c.ev[j].tolerance);
+    h.ev_comp[j] = in_vgpr(c.ev[j].component);
+    h.ev_dir[j] = in_vgpr(c.ev[j].direction);
+  }
+#pragma unroll
+  for (int k = 0; k < AC; ++k) {
+    h.acc_kind[k] = in_vgpr(c.acc[k].kind);
+    h.acc_comp[k] = in_vgpr(c.acc[k].component);
+  }
+  h.n_events = in_vgpr(c.n_events);
+  h.n_acc = in_vgpr(c.n_acc);
+  h.max_eq = in_vgpr(c.max_eq);
+  h.max_steps = in_vgpr(c.max_steps);
+  return h;
+}
+
 template <class M, int METHOD, int PREC, int NEV, int NACC>
 __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   const Control &c = prm.c;
@@ -424,6 +484,8 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     }
     active = false;
   };
+
+  const HotControl<N, EV, AC> hc = hot_control<N, EV, AC>(c);
 
   for (;;) {
     // ---- refill idle lanes from the queue (all 64 lanes are converged here) ----
@@ -533,11 +595,6 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     }
     if (!active) continue;
 
-    // Launch constants are read through a fresh opaque kernel-argument pointer
-    // in every attempt: scalar loads at the point of use, instead of values
-    // held in scalar registers across the loop (which the transcendental
-    // routines' constants would push into vector-register lanes).
-    const ParamsRef kp = fresh_params();
     // ---- choose this attempt's step length ----
     double t_b = t1, h_att;
     bool clipped = false;
@@ -545,17 +602,17 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       h_att = sc;
     } else {
       t_b = (!window_open && t_rec < t1) ? t_rec : t1;
-      if (kp->c.section_period > 0.0) {
-        const double t_sec = __dmul_rn(sec_n, kp->c.section_period);
+      if (hc.section_period > 0.0) {
+        const double t_sec = __dmul_rn(sec_n, hc.section_period);
         t_b = (t_sec < t_b) ? t_sec : t_b;
       }
       if (METHOD == kMethodRK4) {
-        const double t_grid = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), kp->c.h0));
-        if (t_grid >= __dsub_rn(t_b, __dmul_rn(1e-9, kp->c.h0))) {
+        const double t_grid = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), hc.h0));
+        if (t_grid >= __dsub_rn(t_b, __dmul_rn(1e-9, hc.h0))) {
           h_att = t_b - t;
           clipped = true;
         } else {
-          h_att = kp->c.h0;
+          h_att = hc.h0;
         }
       } else {
         h_att = h;
@@ -597,24 +654,24 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
           has_nan |= isnan(yn[i]);
-          const double sc_i = fma(kp->c.rtol[i], fmax(fabs(y[i]), fabs(yn[i])), kp->c.atol[i]);
+          const double sc_i = fma(hc.rtol[i], fmax(fabs(y[i]), fabs(yn[i])), hc.atol[i]);
           const double r = fabs(err[i]) / sc_i;
           has_nan |= isnan(r);
           E = (r > E) ? r : E;
         }
         if (has_nan) {
           passed = false;
-          if (h_att <= kp->c.h_min) {
+          if (h_att <= hc.h_min) {
             status = kFailNan;
           } else {
-            h = fmax(kp->c.h_min, kp->c.shrink * h_att);
+            h = fmax(hc.h_min, hc.shrink * h_att);
             ++n_rej;
           }
         } else {
-          double fac = (E == 0.0) ? kp->c.grow : 0.9 * inv_fifth_root(E);
-          fac = fmax(kp->c.shrink, fmin(kp->c.grow, fac));
-          h_next = fmax(kp->c.h_min, fmin(kp->c.h_max, fac * h_att));
-          if (!(E <= 1.0) && h_att > kp->c.h_min) {
+          double fac = (E == 0.0) ? hc.grow : 0.9 * inv_fifth_root(E);
+          fac = fmax(hc.shrink, fmin(hc.grow, fac));
+          h_next = fmax(hc.h_min, fmin(hc.h_max, fac * h_att));
+          if (!(E <= 1.0) && h_att > hc.h_min) {
             passed = false;
             h = h_next;
             ++n_rej;
@@ -625,9 +682,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
         uint32_t cross = 0, land = 0;
 #pragma unroll
         for (int j = 0; j < NEV; ++j) {
-          if (j < kp->c.n_events && !((leaving >> j) & 1u)) {
-            const double Fn = pick(yn, kp->c.ev[j].component) - kp->c.ev[j].level;
-            const int d = detect(F[j], Fn, kp->c.ev[j].direction, kp->c.ev[j].tolerance);
+          if (j < hc.n_events && !((leaving >> j) & 1u)) {
+            const double Fn = pick(yn, hc.ev_comp[j]) - hc.ev_level[j];
+            const int d = detect(F[j], Fn, hc.ev_dir[j], hc.ev_tol[j]);
             cross |= (d == 1 ? 1u : 0u) << j;
             land |= (d == 2 ? 1u : 0u) << j;
           }
@@ -642,9 +699,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
           for (int j = 0; j < NEV; ++j)
             if (top == (1u << j)) {
-              loc_c = kp->c.ev[j].component;
-              loc_level = kp->c.ev[j].level;
-              loc_tol = kp->c.ev[j].tolerance;
+              loc_c = hc.ev_comp[j];
+              loc_level = hc.ev_level[j];
+              loc_tol = hc.ev_tol[j];
               ga = F[j];
             }
           gb = pick(yn, loc_c) - loc_level;
@@ -661,7 +718,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
           if (clipped)
             tn = t_b;
           else if (METHOD == kMethodRK4)
-            tn = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), kp->c.h0));
+            tn = __dadd_rn(seg_start, __dmul_rn((double)(seg_steps + 1), hc.h0));
           else
             tn = t + h_att;
           if (METHOD == kMethodRKCK45) {
@@ -686,9 +743,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
         det = loc_bit;
 #pragma unroll
         for (int j = 0; j < NEV; ++j) {
-          if (j < kp->c.n_events && (1u << j) != loc_bit && !((leaving >> j) & 1u)) {
-            const double Fn = pick(yn, kp->c.ev[j].component) - kp->c.ev[j].level;
-            det |= (detect(F[j], Fn, kp->c.ev[j].direction, kp->c.ev[j].tolerance) != 0 ? 1u : 0u) << j;
+          if (j < hc.n_events && (1u << j) != loc_bit && !((leaving >> j) & 1u)) {
+            const double Fn = pick(yn, hc.ev_comp[j]) - hc.ev_level[j];
+            det |= (detect(F[j], Fn, hc.ev_dir[j], hc.ev_tol[j]) != 0 ? 1u : 0u) << j;
           }
         }
       } else {
@@ -727,9 +784,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       } else {
 #pragma unroll
         for (int k = 0; k < NACC; ++k)
-          if (k < kp->c.n_acc && kp->c.acc[k].kind != kAccLogReset) {
-            const double v = pick(y, kp->c.acc[k].component);
-            const bool better = (kp->c.acc[k].kind == kAccMax) ? (v > accv[k]) : (v < accv[k]);
+          if (k < hc.n_acc && hc.acc_kind[k] != kAccLogReset) {
+            const double v = pick(y, hc.acc_comp[k]);
+            const bool better = (hc.acc_kind[k] == kAccMax) ? (v > accv[k]) : (v < accv[k]);
             accv[k] = better ? v : accv[k];
             acct[k] = better ? t : acct[k];
           }
@@ -765,11 +822,11 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       // Poincare section reached (the step was clipped to it): the Lyapunov
       // accumulators add ln y[c] for sections after the window start, and
       // y[c] restarts from 1 at every section (paper Sec. 2.1)
-      if (kp->c.section_period > 0.0 && t == __dmul_rn(sec_n, kp->c.section_period)) {
+      if (hc.section_period > 0.0 && t == __dmul_rn(sec_n, hc.section_period)) {
 #pragma unroll
         for (int k = 0; k < NACC; ++k)
-          if (k < kp->c.n_acc && kp->c.acc[k].kind == kAccLogReset) {
-            const int comp = kp->c.acc[k].component;
+          if (k < hc.n_acc && hc.acc_kind[k] == kAccLogReset) {
+            const int comp = hc.acc_comp[k];
             if (window_open && t > t_rec) {
               accv[k] = accv[k] + log(pick(y, comp));
               acct[k] = acct[k] + 1.0;
@@ -782,16 +839,16 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       // that stay inside after a detection count towards the equilibrium stop
 #pragma unroll
       for (int j = 0; j < NEV; ++j) {
-        if (j < kp->c.n_events) {
-          F[j] = pick(y, kp->c.ev[j].component) - kp->c.ev[j].level;
-          const bool inside = fabs(F[j]) <= kp->c.ev[j].tolerance;
+        if (j < hc.n_events) {
+          F[j] = pick(y, hc.ev_comp[j]) - hc.ev_level[j];
+          const bool inside = fabs(F[j]) <= hc.ev_tol[j];
           const uint32_t bit = 1u << j;
           if (((det | ~leaving) & bit) != 0) {
             leaving = inside ? (leaving | bit) : (leaving & ~bit);
             zone[j] = 0;
           } else if (inside) {
             ++zone[j];
-            if (kp->c.max_eq > 0 && zone[j] >= kp->c.max_eq && status == kRunning)
+            if (hc.max_eq > 0 && zone[j] >= hc.max_eq && status == kRunning)
               status = kStopEquilibrium;
           } else {
             leaving &= ~bit;
@@ -801,7 +858,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       }
       if (status == kRunning && t >= t1) status = kDone;
     }
-    if (status == kRunning && !locating && attempts >= kp->c.max_steps) status = kMaxSteps;
+    if (status == kRunning && !locating && attempts >= hc.max_steps) status = kMaxSteps;
     if (status != kRunning) retire();
   }
 

@@ -21,7 +21,7 @@ struct Duffing {
 #pragma unroll
     for (int k = 0; k < S; ++k) arg[k] = __dmul_rn(p[2], ts[k]);
     double sb, cb;
-    sincos(arg[0], &sb, &cb);
+    sincos_cw(arg[0], sb, cb);
     stage_sincos<S>(arg, sb, cb, sn, cs);
 #pragma unroll
     for (int k = 0; k < S; ++k) F[k][0] = cs[k];

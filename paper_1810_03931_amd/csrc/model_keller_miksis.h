@@ -26,8 +26,8 @@ struct KellerMiksis {
       a2[k] = __dadd_rn(__dmul_rn(w2, ts[k]), C[12]);
     }
     double s1b, c1b, s2b, c2b;
-    sincos(a1[0], &s1b, &c1b);
-    sincos(a2[0], &s2b, &c2b);
+    sincos_cw(a1[0], s1b, c1b);
+    sincos_cw(a2[0], s2b, c2b);
     stage_sincos<S>(a1, s1b, c1b, s1, c1);
     stage_sincos<S>(a2, s2b, c2b, s2, c2);
 #pragma unroll

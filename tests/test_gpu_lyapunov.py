@@ -64,14 +64,24 @@ def test_full_horizon_sampled(ode, oracle):
     sample = I.stratified_sample(pb.n, 192, seed=12)
     sub = pb.subset(sample)
     o = run_oracle(sub)
+    # Two twins screen for systems whose answer the definition fixes: one moves
+    # the initial state by 1e-9, the other scales the forcing amplitude B by
+    # one ulp, a rounding-level change of the right-hand side at every step
+    # (the GPU evaluates the forcing with other roundings than libm).
     twin = sub.copy()
     twin.state[:2] = twin.state[:2] * (1.0 + 1e-9) + 1e-12
     ot = run_oracle(twin)
+    twin_b = sub.copy()
+    twin_b.params = twin_b.params.copy()
+    twin_b.params[1] = twin_b.params[1] * (1.0 + 2.0 ** -52)
+    ob = run_oracle(twin_b)
     gs = take(g, sample)
     assert np.array_equal(gs["status"], o["status"])
-    dist = np.abs(ot["acc"][0] - o["acc"][0]) / np.maximum(np.abs(o["acc"][0]), 1.0)
-    dist = np.maximum(dist, np.max(np.abs(ot["y"][:2] - o["y"][:2]), axis=0)
-                      / np.maximum(np.max(np.abs(o["y"][:2]), axis=0), 1.0))
+    dist = np.zeros(len(sample))
+    for tw in (ot, ob):
+        dist = np.maximum(dist, np.abs(tw["acc"][0] - o["acc"][0]) / np.maximum(np.abs(o["acc"][0]), 1.0))
+        dist = np.maximum(dist, np.max(np.abs(tw["y"][:2] - o["y"][:2]), axis=0)
+                          / np.maximum(np.max(np.abs(o["y"][:2]), axis=0), 1.0))
     stable = dist <= 1e-9
     ea = np.abs(gs["acc"][0] - o["acc"][0]) / np.maximum(np.abs(o["acc"][0]), 1.0)
     lam_g = gs["acc"][0] / (gs["acc"][1] * T)
