@@ -440,6 +440,8 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   for (int k = 0; k < AC; ++k) accv[k] = acct[k] = 0.0;
 
   bool exhausted = false;  // wave-uniform
+  bool first_fill = true;  // wave-uniform
+  const uint32_t wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   uint32_t iter = 0;       // loop iterations of this wave (wave-uniform)
 
   auto acc_init = [&]() {
@@ -495,11 +497,28 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       const Arrays a = arrays_of(q);
       const int64_t ld = a.ld;
       const uint32_t k = __popcll(need);
+      const unsigned long long fixed = (unsigned long long)a.total_waves * 64ull;
       unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)k);
-      base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
-             (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base);
-      if (base + k >= (unsigned long long)a.n) exhausted = true;
+      if (first_fill) {
+        // The first 64 queue positions of a wave follow from its place in the
+        // grid.  Workgroups are dealt round-robin to the XCDs, so each XCD
+        // gets every eighth group of 256 positions, an even sample of the
+        // queue order.  Claimed through the counter instead, the first
+        // positions reach the XCDs in contiguous stretches (the order in which
+        // their waves happen to start), and a sweep whose cost varies along
+        // its index left some XCDs with twice the work of others (Duffing
+        // sweep: XCDs finishing between 0.45 and 0.97 s).
+        first_fill = false;
+        base = (unsigned long long)wave_id * 64ull;
+        if (fixed >= (unsigned long long)a.n) exhausted = true;
+      } else {
+        // later positions are claimed in queue order through the counter
+        if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)k);
+        base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+               (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base);
+        base += fixed;
+        if (base + k >= (unsigned long long)a.n) exhausted = true;
+      }
       if (!active) {
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
