@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="repeated-horizon workloads: time the host loop of solve calls "
                          "instead of the recorded graph")
+    ap.add_argument("--plan", type=float, default=-1.0, metavar="FRACTION",
+                    help="plan the queue order inside every timed step from a probe over this "
+                         "fraction of the horizon (ode_ensemble_plan); -1: 0.02 when every system "
+                         "is resident and two or more waves share each SIMD, 0: never")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=0.0,
                     help="override rtol = atol of the sweep (0: the sweep's own)")
@@ -275,21 +279,41 @@ def main():
                 snaps[k - first, :2].copy_(y)
                 snaps[k - first, 2:].copy_(out["acc"])
 
+    plan_frac = 0.0
+    plan_ms = []
+
     def step():
         td.copy_(td0)
         y.copy_(y0)
+        index = None
+        if plan_frac > 0:
+            t_plan = time.perf_counter()
+            index = ens.plan(td, y, p, probe_fraction=plan_frac, stream=stream, **pb.options)
+            plan_ms.append((time.perf_counter() - t_plan) * 1e3)
         k0 = torch.cuda.Event(enable_timing=True)
         k1 = torch.cuda.Event(enable_timing=True)
         k0.record(stream)
         if segments is None:
-            ens.solve(td, y, p, out=out, stream=stream, **pb.options)
+            ens.solve(td, y, p, out=out, system_index=index, stream=stream, **pb.options)
         else:
             run_segments()
         k1.record(stream)
         return k0, k1
 
+    if args.plan > 0:
+        plan_frac = args.plan
+    elif args.plan < 0 and segments is None and args.uniform < 0 and pb.method == "rkck45":
+        # an untimed launch first tells the residency: plan when every system
+        # has a lane from the start and two or more waves share each SIMD
+        step()
+        torch.cuda.synchronize()
+        info0 = ens.info()
+        waves_per_simd = pb.n / (64.0 * 4 * max(info0["compute_units"], 1))
+        if pb.n <= info0["resident_systems"] and waves_per_simd >= 2:
+            plan_frac = 0.02
     for _ in range(args.warmup):
         step()
+    plan_ms.clear()
     torch.cuda.synchronize()
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
@@ -343,6 +367,9 @@ def main():
                    "rtol": pb.options.get("rtol"), "precision": args.precision,
                    "block_size": info["block_size"], "blocks_per_cu": info["blocks_per_cu"],
                    "resident_systems": info["resident_systems"], "tuned": tuned is not None,
+                   "queue_plan": ({"probe_fraction": plan_frac,
+                                   "plan_ms": float(np.mean(plan_ms)) if plan_ms else None,
+                                   "timed": True} if plan_frac > 0 else None),
                    **({"segments": n_seg, "launch": "host loop" if args.eager else "HIP graph"}
                       if segments is not None else {})},
         "attempted_steps_per_s": attempts / (ms_per_step / 1e3),

@@ -284,6 +284,50 @@ typedef struct {
 int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *args, double probe_fraction,
                       void *hip_stream, ode_tune_result *result);
 
+/* Queue order for a solve, from per-system cost estimates.  The paper's
+ * warps run as long as their slowest thread (Sec. 7.1.1, 7.2-7.3); here a
+ * SIMD runs as long as the chains of the waves resident on it together, and
+ * with every system resident from the start the queue order decides which
+ * systems share a SIMD.
+ *
+ * Host only, no GPU: cost[q] (q < n) estimates the work of queue position q
+ * (e.g. its attempted steps over part of the horizon) and queue[q] is the
+ * system at position q (NULL: q itself).  The positions are taken in chunks
+ * of 64 (one wave), a chunk costing its largest entry, and sorted by cost,
+ * most expensive first (ties keep their order).
+ *  - If waves * 64 >= n (every position has a lane from the start: wave w of
+ *    the launch takes positions 64w .. 64w+63), the sorted chunks are dealt
+ *    to the waves in rounds of round_waves (one wave per SIMD across the
+ *    chip; a wave's SIMD partners are the waves at the same place in the
+ *    other rounds), in alternating direction, so that a SIMD's waves get one
+ *    long and one short chunk.  *n_out = waves * 64; positions no chunk
+ *    reaches hold -1 (the solve skips negative entries).
+ *  - Otherwise the lanes take positions as they free up: the chunks follow
+ *    each other in sorted order (longest processing time first), *n_out = n.
+ * n == 0 gives *n_out = 0.  out (capacity entries, host) receives the
+ * system per position; out NULL only sets *n_out.  Errors: ODE_EINVAL (n < 0, waves or round_waves < 1,
+ * cost NULL with n > 0, n_out NULL, capacity < *n_out). */
+int ode_plan_order(const int64_t *cost, const int64_t *queue, int64_t n, int64_t waves,
+                   int64_t round_waves, int64_t *out, int64_t capacity, int64_t *n_out);
+
+/* Plan the queue order of a solve on this handle (ode_plan_order on measured
+ * costs).  A probe integrates the problem of `args` over the first
+ * probe_fraction of each system's time domain, on private copies of every
+ * array the solve writes (the caller's arrays are only read), with the
+ * handle's launch configuration; a position's cost is its system's attempted
+ * steps in the probe.  waves is the solve's launch size and round_waves is
+ * 4 x the device's compute units.  The order is written to index_out (device,
+ * capacity int64 entries) and its length to *n_positions; pass index_out as
+ * args->system_index and *n_positions as args->n_systems of the solve (same
+ * handle, same other arguments).  Each system's results are bit-identical to
+ * those of the unplanned solve; only its lane changes.  index_out NULL only
+ * sets *n_positions (no probe).  Synchronous.  Allocates and frees device
+ * memory for the copies.  0 < probe_fraction <= 1.  Errors: ODE_EINVAL,
+ * ODE_ENOMEM, ODE_EHIP. */
+int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *args, double probe_fraction,
+                      int64_t *index_out, int64_t capacity, int64_t *n_positions,
+                      void *hip_stream);
+
 /* Launch facts for the handle.  Errors: ODE_EINVAL for NULL arguments. */
 int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info);
 

@@ -4,12 +4,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "integrator.h"
 
@@ -578,6 +580,92 @@ int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *a, double probe_fra
   result->candidates = n_tried;
   result->best_ms = best;
   result->default_ms = base;
+  return ODE_OK;
+}
+
+
+int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *a, double probe_fraction,
+                      int64_t *index_out, int64_t capacity, int64_t *n_positions,
+                      void *hip_stream) {
+  if (!e || !a || !n_positions) return fail(ODE_EINVAL, "NULL handle, arguments or n_positions");
+  int rc = validate(e, a);
+  if (rc != ODE_OK) return rc;
+  if (!(probe_fraction > 0.0 && probe_fraction <= 1.0))
+    return fail(ODE_EINVAL, "probe_fraction must be in (0, 1]");
+  const int64_t n = a->n_systems, ld = a->ld;
+  int bpc = 0;
+  rc = query_blocks(e, e->block, event_slots(a->n_events), acc_slots(a->n_accessories), &bpc);
+  if (rc != ODE_OK) return rc;
+  const int64_t max_grid = (int64_t)bpc * e->compute_units;
+  const int64_t need = (n + e->block - 1) / e->block;
+  const int64_t waves = std::max<int64_t>(1, std::min(need, max_grid)) * (e->block / 64);
+  const int64_t round_waves = 4 * (int64_t)e->compute_units;  // one wave on every SIMD
+  const int64_t total = n == 0 ? 0 : (waves * 64 >= n ? waves * 64 : n);
+  *n_positions = total;
+  if (!index_out || n == 0) return ODE_OK;
+  if (capacity < total)
+    return fail(ODE_EINVAL, "index capacity %lld < %lld positions", (long long)capacity,
+                (long long)total);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+  // the probe: the problem over the first probe_fraction of each horizon, on
+  // private copies of every array the solve writes
+  ProbeArrays c;
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t x) { if (err == hipSuccess) err = x; };
+  chk(alloc(&c.td, 2 * ld));
+  chk(alloc(&c.y, (int64_t)e->n_state * ld));
+  chk(alloc(&c.status, ld));
+  chk(alloc(&c.counts, 3 * ld));
+  if (a->n_accessories) chk(alloc(&c.acc, 2 * (int64_t)a->n_accessories * ld));
+  if (a->next_h) chk(alloc(&c.next_h, ld));
+  if (a->n_events) chk(alloc(&c.evc, (int64_t)a->n_events * ld));
+  if (a->event_record_capacity) chk(alloc(&c.rec, 2 * (int64_t)a->event_record_capacity * ld));
+  if (err != hipSuccess)
+    return fail(ODE_ENOMEM, "allocating the probe copies: %s", hipGetErrorString(err));
+  ode_solve_args pa = *a;
+  pa.time_domain = c.td;
+  pa.state = c.y;
+  pa.accessories = c.acc;
+  pa.next_h = c.next_h;
+  pa.status = c.status;
+  pa.counts = c.counts;
+  pa.event_counts = c.evc;
+  pa.event_records = c.rec;
+  hipError_t x = launch_probe_horizon(a->time_domain, c.td, ld, n, a->system_index,
+                                      probe_fraction, st);
+  if (x == hipSuccess)
+    x = hipMemcpyAsync(c.y, a->state, sizeof(double) * e->n_state * ld, hipMemcpyDeviceToDevice, st);
+  if (x == hipSuccess && a->next_h)
+    x = hipMemcpyAsync(c.next_h, a->next_h, sizeof(double) * ld, hipMemcpyDeviceToDevice, st);
+  if (x != hipSuccess) return hip_fail(x, "preparing the probe");
+  Params prm;
+  int nev = 0, nacc = 0, grid = 0;
+  rc = prepare_launch(e, &pa, prm, nev, nacc, grid);
+  if (rc != ODE_OK) return rc;
+  x = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid, e->block, st);
+  if (x != hipSuccess) return hip_fail(x, "launching the probe");
+
+  // per-position cost: the probe's attempts of the position's system
+  std::vector<int64_t> counts(3 * ld), queue, cost(n, 0), order(total);
+  x = hipMemcpyAsync(counts.data(), c.counts, sizeof(int64_t) * 3 * ld, hipMemcpyDeviceToHost, st);
+  if (x == hipSuccess && a->system_index) {
+    queue.resize(n);
+    x = hipMemcpyAsync(queue.data(), a->system_index, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st);
+  }
+  if (x == hipSuccess) x = hipStreamSynchronize(st);
+  if (x != hipSuccess) return hip_fail(x, "reading the probe counts");
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t s = queue.empty() ? q : queue[q];
+    if (s >= 0 && s < ld) cost[q] = counts[s] + counts[ld + s] + counts[2 * ld + s];
+  }
+  int64_t written = 0;
+  if (ode_plan_order(cost.data(), queue.empty() ? nullptr : queue.data(), n, waves, round_waves,
+                     order.data(), total, &written) != ODE_OK || written != total)
+    return fail(ODE_EINVAL, "planner arguments");
+  x = hipMemcpyAsync(index_out, order.data(), sizeof(int64_t) * total, hipMemcpyHostToDevice, st);
+  if (x == hipSuccess) x = hipStreamSynchronize(st);
+  if (x != hipSuccess) return hip_fail(x, "writing the plan");
   return ODE_OK;
 }
 

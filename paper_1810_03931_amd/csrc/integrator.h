@@ -63,9 +63,7 @@ struct Arrays {
   const int64_t *index;
   const double *t_rec;  // per-system window start, or nullptr (Control::t_record)
   int64_t n, ld;
-  // [0] queue positions claimed after each wave's fixed first 64
-  // (total_waves * 64 + [0] is the next one), [1] finished waves
-  unsigned long long *queue;
+  unsigned long long *queue;  // [0] next queue position, [1] finished waves
   uint32_t total_waves;
 };
 

@@ -497,28 +497,26 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       const Arrays a = arrays_of(q);
       const int64_t ld = a.ld;
       const uint32_t k = __popcll(need);
-      const unsigned long long fixed = (unsigned long long)a.total_waves * 64ull;
       unsigned long long base = 0;
-      if (first_fill) {
-        // The first 64 queue positions of a wave follow from its place in the
-        // grid.  Workgroups are dealt round-robin to the XCDs, so each XCD
-        // gets every eighth group of 256 positions, an even sample of the
-        // queue order.  Claimed through the counter instead, the first
-        // positions reach the XCDs in contiguous stretches (the order in which
-        // their waves happen to start), and a sweep whose cost varies along
-        // its index left some XCDs with twice the work of others (Duffing
-        // sweep: XCDs finishing between 0.45 and 0.97 s).
-        first_fill = false;
+      if (first_fill && (unsigned long long)a.total_waves * 64ull >= (unsigned long long)a.n) {
+        // Every system has a lane from the start: wave w takes queue
+        // positions 64w .. 64w + 63, so the queue order decides which systems
+        // share a SIMD.  The waves of the first 256 workgroups (one per CU)
+        // share their SIMDs with those of the next 256, one wave each; a
+        // caller that knows the systems' costs can order the queue so that
+        // each SIMD gets one long and one short chunk.
         base = (unsigned long long)wave_id * 64ull;
-        if (fixed >= (unsigned long long)a.n) exhausted = true;
+        exhausted = true;
       } else {
-        // later positions are claimed in queue order through the counter
+        // with more systems than lanes the counter hands out positions in
+        // queue order (an input sorted heaviest first stays so), and refills
+        // balance the XCDs
         if (lane == 0) base = atomicAdd(a.queue, (unsigned long long)k);
         base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
                (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base);
-        base += fixed;
         if (base + k >= (unsigned long long)a.n) exhausted = true;
       }
+      first_fill = false;
       if (!active) {
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));

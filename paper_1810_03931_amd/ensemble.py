@@ -84,10 +84,31 @@ class Info(C.Structure):
 
 
 EXPORTS = ("ode_ensemble_model_dims", "ode_ensemble_create", "ode_ensemble_solve",
-           "ode_ensemble_solve_segments", "ode_ensemble_tune", "ode_ensemble_query",
-           "ode_ensemble_destroy", "ode_ensemble_last_error")
+           "ode_ensemble_solve_segments", "ode_ensemble_tune", "ode_ensemble_plan",
+           "ode_plan_order", "ode_ensemble_query", "ode_ensemble_destroy",
+           "ode_ensemble_last_error")
 
 _lib = None
+
+
+def plan_order(cost, waves: int, round_waves: int, queue=None):
+    """Host-only queue order from per-position costs (``ode_plan_order``):
+    numpy int64 ``cost`` [n] and optional ``queue`` [n] -> int64 order."""
+    import numpy as np
+    cost = np.ascontiguousarray(cost, dtype=np.int64)
+    q = None if queue is None else np.ascontiguousarray(queue, dtype=np.int64)
+    if q is not None and q.size != cost.size:
+        raise ValueError("queue: need one entry per cost")
+    lib = load_library()
+    total = C.c_int64(0)
+    args = (cost.ctypes.data, None if q is None else q.ctypes.data, cost.size, int(waves),
+            int(round_waves))
+    if lib.ode_plan_order(*args, None, 0, C.byref(total)) != OK:
+        raise OdeError(EINVAL, "ode_plan_order: invalid arguments")
+    out = np.empty(max(total.value, 1), dtype=np.int64)
+    if lib.ode_plan_order(*args, out.ctypes.data, out.size, C.byref(total)) != OK:
+        raise OdeError(EINVAL, "ode_plan_order: invalid arguments")
+    return out[:total.value]
 
 
 def load_library(path: str = LIB_PATH):
@@ -110,6 +131,12 @@ def load_library(path: str = LIB_PATH):
     L.ode_ensemble_tune.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_double, C.c_void_p,
                                     C.POINTER(TuneResult)]
     L.ode_ensemble_tune.restype = C.c_int
+    L.ode_ensemble_plan.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_double, C.c_void_p,
+                                    C.c_int64, C.POINTER(C.c_int64), C.c_void_p]
+    L.ode_ensemble_plan.restype = C.c_int
+    L.ode_plan_order.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                 C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
+    L.ode_plan_order.restype = C.c_int
     L.ode_ensemble_query.argtypes = [C.c_void_p, C.POINTER(Info)]
     L.ode_ensemble_query.restype = C.c_int
     L.ode_ensemble_destroy.argtypes = [C.c_void_p]
@@ -299,6 +326,28 @@ class Ensemble:
         _check(load_library().ode_ensemble_tune(self._h, C.byref(a), float(probe_fraction),
                                                 C.c_void_p(stream.cuda_stream), C.byref(r)))
         return {f: getattr(r, f) for f, _ in TuneResult._fields_ if f != "reserved"}
+
+    def plan(self, time_domain, state, params, *, probe_fraction: float = 0.02, next_h=None,
+             system_index=None, stream=None, **options: Any):
+        """Queue order for a solve of this problem on this handle: a probe on
+        private copies over the first ``probe_fraction`` of each horizon
+        measures every system's cost, and 64-system chunks are dealt so that
+        the waves sharing a SIMD get a long and a short one.  Returns a CUDA
+        int64 tensor to pass as ``system_index`` to :meth:`solve` (same other
+        arguments); results are bit-identical to the unplanned solve."""
+        import torch
+        a, _, _ = self._args(time_domain, state, params, next_h, system_index, None, options)
+        if stream is None:
+            stream = torch.cuda.current_stream(time_domain.device)
+        lib = load_library()
+        total = C.c_int64(0)
+        _check(lib.ode_ensemble_plan(self._h, C.byref(a), float(probe_fraction), None, 0,
+                                     C.byref(total), C.c_void_p(stream.cuda_stream)))
+        index = torch.empty(max(total.value, 1), dtype=torch.int64, device=time_domain.device)
+        _check(lib.ode_ensemble_plan(self._h, C.byref(a), float(probe_fraction),
+                                     C.c_void_p(index.data_ptr()), index.numel(), C.byref(total),
+                                     C.c_void_p(stream.cuda_stream)))
+        return index[:total.value]
 
     def solve_segments(self, time_domain, state, params, n_segments: int, segment: float, *,
                        first_snapshot: int = 0, snapshots=None, next_h=None, system_index=None,
