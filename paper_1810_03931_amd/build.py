@@ -27,15 +27,23 @@ FLAGS = [
 ]
 
 
-# Per-translation-unit flags.  The Keller-Miksis sweep is bound by the latency
-# of one attempt on nearly empty waves: it ends with a few long serial chains.
-# LLVM's scheduler tuned for instruction-level parallelism instead of
-# occupancy shortens that latency.  It uses 258 registers, so one wave per
-# SIMD instead of two, and lock-step throughput drops from 45% to 34% of the
-# FP64 peak; but the sweep, whose time is its slowest chains, runs ~20% faster
-# (22-26 s against 27-32 s).  The other kernels gain nothing from it.
+# Per-translation-unit flags: LLVM's scheduler tuned for instruction-level
+# parallelism instead of occupancy, where a sweep's end is set by waves that
+# run alone on their SIMD.
+#  * Keller-Miksis is bound by a few long serial chains.  The schedule uses
+#    258 registers, so one wave per SIMD instead of two; lock-step throughput
+#    drops from 45% to 34% of the FP64 peak, but the sweep runs ~20% faster
+#    (22-26 s against 27-32 s).
+#  * Duffing and the relief valve keep two waves per SIMD (239 and 228
+#    registers for the swept kernels).  Once a planned sweep's shorter wave
+#    ends, the longer one runs alone, and it runs faster with this schedule:
+#    758-771 against 779-786 ms, and 2432-2438 against 2488-2498 ms.
+#  * The Lyapunov kernel (one wave per SIMD) gains nothing: 436 against 437 ms.
+_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 TU_FLAGS = {
-    "kernels_keller_miksis.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "kernels_keller_miksis.hip": _ILP,
+    "kernels_duffing.hip": _ILP,
+    "kernels_relief_valve.hip": _ILP,
 }
 
 
