@@ -26,8 +26,10 @@ namespace odeens {
 // error of the leading subtraction.  The quadrant k mod 4 swaps and negates.
 // Measured against 60-digit values: p99 0.57 ulp, at most 0.7 ulp away from
 // the zeros (relative error up to 1.13 ulp right next to them, i.e. below
-// 1e-29 absolute).  Beyond |x| = 1e6 the library routine is used.
-__device__ __forceinline__ void sincos_cw(double x, double &s, double &c) {
+// 1e-29 absolute).  Beyond |x| = 1e6 the library routine is used.  Also
+// compiled for the host, where a test checks these bounds against 60-digit
+// values.
+__host__ __device__ __forceinline__ void sincos_cw(double x, double &s, double &c) {
   if (!(fabs(x) <= 1e6)) {
     sincos(x, &s, &c);
     return;
