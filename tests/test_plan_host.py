@@ -31,7 +31,7 @@ def test_resident_deal_pairs_long_with_short(n):
             cc[w] = cost[v].max()
         else:
             cc[w] = 0
-    # partners: wave w of round 0 shares a SIMD with wave w of round 1
+    # partners: wave w of the first dispatch round shares a SIMD with wave w of the second
     pair = np.array([cc[w] + cc[w + rw] for w in range(rw)])
     chunk_cost = np.array([cost[c].max() for c in _chunks(n)])
     srt = np.sort(chunk_cost)[::-1]
@@ -63,7 +63,7 @@ def test_ties_keep_order_and_rounds_alternate():
     n, waves, rw = 64 * 8, 8, 4
     out = E.plan_order(np.ones(n, dtype=np.int64), waves, rw)
     first = out.reshape(waves, 64)[:, 0] // 64
-    # equal costs: chunk ranks 0..3 forward in round 0, 4..7 backward in round 1
+    # equal costs: chunk ranks 0..3 forward in the first dispatch round, 4..7 backward in the second
     assert list(first) == [0, 1, 2, 3, 7, 6, 5, 4]
 
 
