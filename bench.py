@@ -63,8 +63,11 @@ def parse():
                          "instead of the recorded graph")
     ap.add_argument("--plan", type=float, default=-1.0, metavar="FRACTION",
                     help="plan the queue order inside every timed step from a probe over this "
-                         "fraction of the horizon (ode_ensemble_plan); -1: 0.02 when every system "
-                         "is resident and two or more waves share each SIMD, 0: never")
+                         "fraction of the horizon at 100x the tolerances (ode_ensemble_plan); "
+                         "-1: 0.04 when every system is resident and two or more waves share "
+                         "each SIMD, 0: never")
+    ap.add_argument("--plan-tol-scale", type=float, default=100.0, metavar="S",
+                    help="the plan's probe runs at S times the tolerances")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=0.0,
                     help="override rtol = atol of the sweep (0: the sweep's own)")
@@ -288,7 +291,9 @@ def main():
         index = None
         if plan_frac > 0:
             t_plan = time.perf_counter()
-            index = ens.plan(td, y, p, probe_fraction=plan_frac, stream=stream, **pb.options)
+            index = ens.plan(td, y, p, probe_fraction=plan_frac,
+                             probe_tolerance_scale=args.plan_tol_scale, stream=stream,
+                             **pb.options)
             plan_ms.append((time.perf_counter() - t_plan) * 1e3)
         k0 = torch.cuda.Event(enable_timing=True)
         k1 = torch.cuda.Event(enable_timing=True)
@@ -310,7 +315,7 @@ def main():
         info0 = ens.info()
         waves_per_simd = pb.n / (64.0 * 4 * max(info0["compute_units"], 1))
         if pb.n <= info0["resident_systems"] and waves_per_simd >= 2:
-            plan_frac = 0.02
+            plan_frac = 0.04
     for _ in range(args.warmup):
         step()
     plan_ms.clear()
@@ -368,6 +373,7 @@ def main():
                    "block_size": info["block_size"], "blocks_per_cu": info["blocks_per_cu"],
                    "resident_systems": info["resident_systems"], "tuned": tuned is not None,
                    "queue_plan": ({"probe_fraction": plan_frac,
+                                   "probe_tolerance_scale": args.plan_tol_scale,
                                    "plan_ms": float(np.mean(plan_ms)) if plan_ms else None,
                                    "timed": True} if plan_frac > 0 else None),
                    **({"segments": n_seg, "launch": "host loop" if args.eager else "HIP graph"}

@@ -312,21 +312,23 @@ int ode_plan_order(const int64_t *cost, const int64_t *queue, int64_t n, int64_t
 
 /* Plan the queue order of a solve on this handle (ode_plan_order on measured
  * costs).  A probe integrates the problem of `args` over the first
- * probe_fraction of each system's time domain, on private copies of every
- * array the solve writes (the caller's arrays are only read), with the
- * handle's launch configuration; a position's cost is its system's attempted
- * steps in the probe.  waves is the solve's launch size and round_waves is
+ * probe_fraction of each system's time domain, with rtol and atol multiplied
+ * by probe_tolerance_scale (RKCK45 step counts scale alike across systems, so
+ * a looser probe covers more of the horizon for the same work), on private
+ * copies of every array the solve writes (the caller's arrays are only read),
+ * with the handle's launch configuration; a position's cost is its system's
+ * attempted steps in the probe.  waves is the solve's launch size and round_waves is
  * 4 x the device's compute units.  The order is written to index_out (device,
  * capacity int64 entries) and its length to *n_positions; pass index_out as
  * args->system_index and *n_positions as args->n_systems of the solve (same
  * handle, same other arguments).  Each system's results are bit-identical to
  * those of the unplanned solve; only its lane changes.  index_out NULL only
  * sets *n_positions (no probe).  Synchronous.  Allocates and frees device
- * memory for the copies.  0 < probe_fraction <= 1.  Errors: ODE_EINVAL,
- * ODE_ENOMEM, ODE_EHIP. */
+ * memory for the copies.  0 < probe_fraction <= 1, probe_tolerance_scale >= 1
+ * and finite.  Errors: ODE_EINVAL, ODE_ENOMEM, ODE_EHIP. */
 int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *args, double probe_fraction,
-                      int64_t *index_out, int64_t capacity, int64_t *n_positions,
-                      void *hip_stream);
+                      double probe_tolerance_scale, int64_t *index_out, int64_t capacity,
+                      int64_t *n_positions, void *hip_stream);
 
 /* Launch facts for the handle.  Errors: ODE_EINVAL for NULL arguments. */
 int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info);

@@ -585,13 +585,15 @@ int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *a, double probe_fra
 
 
 int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *a, double probe_fraction,
-                      int64_t *index_out, int64_t capacity, int64_t *n_positions,
-                      void *hip_stream) {
+                      double probe_tolerance_scale, int64_t *index_out, int64_t capacity,
+                      int64_t *n_positions, void *hip_stream) {
   if (!e || !a || !n_positions) return fail(ODE_EINVAL, "NULL handle, arguments or n_positions");
   int rc = validate(e, a);
   if (rc != ODE_OK) return rc;
   if (!(probe_fraction > 0.0 && probe_fraction <= 1.0))
     return fail(ODE_EINVAL, "probe_fraction must be in (0, 1]");
+  if (!(probe_tolerance_scale >= 1.0) || !std::isfinite(probe_tolerance_scale))
+    return fail(ODE_EINVAL, "probe_tolerance_scale must be finite and >= 1");
   const int64_t n = a->n_systems, ld = a->ld;
   int bpc = 0;
   rc = query_blocks(e, e->block, event_slots(a->n_events), acc_slots(a->n_accessories), &bpc);
@@ -632,6 +634,10 @@ int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *a, double probe_fra
   pa.counts = c.counts;
   pa.event_counts = c.evc;
   pa.event_records = c.rec;
+  for (int i = 0; i < ODE_MAX_STATE; ++i) {
+    pa.rtol[i] = a->rtol[i] * probe_tolerance_scale;
+    pa.atol[i] = a->atol[i] * probe_tolerance_scale;
+  }
   hipError_t x = launch_probe_horizon(a->time_domain, c.td, ld, n, a->system_index,
                                       probe_fraction, st);
   if (x == hipSuccess)

@@ -131,8 +131,8 @@ def load_library(path: str = LIB_PATH):
     L.ode_ensemble_tune.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_double, C.c_void_p,
                                     C.POINTER(TuneResult)]
     L.ode_ensemble_tune.restype = C.c_int
-    L.ode_ensemble_plan.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_double, C.c_void_p,
-                                    C.c_int64, C.POINTER(C.c_int64), C.c_void_p]
+    L.ode_ensemble_plan.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_double, C.c_double,
+                                    C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p]
     L.ode_ensemble_plan.restype = C.c_int
     L.ode_plan_order.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                                  C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
@@ -327,13 +327,15 @@ class Ensemble:
                                                 C.c_void_p(stream.cuda_stream), C.byref(r)))
         return {f: getattr(r, f) for f, _ in TuneResult._fields_ if f != "reserved"}
 
-    def plan(self, time_domain, state, params, *, probe_fraction: float = 0.02, next_h=None,
-             system_index=None, stream=None, **options: Any):
+    def plan(self, time_domain, state, params, *, probe_fraction: float = 0.04,
+             probe_tolerance_scale: float = 100.0, next_h=None, system_index=None, stream=None,
+             **options: Any):
         """Queue order for a solve of this problem on this handle: a probe on
-        private copies over the first ``probe_fraction`` of each horizon
-        measures every system's cost, and 64-system chunks are dealt so that
-        the waves sharing a SIMD get a long and a short one.  Returns a CUDA
-        int64 tensor to pass as ``system_index`` to :meth:`solve` (same other
+        private copies over the first ``probe_fraction`` of each horizon, with
+        the tolerances multiplied by ``probe_tolerance_scale``, measures every
+        system's cost, and 64-system chunks are dealt so that the waves
+        sharing a SIMD get a long and a short one.  Returns a CUDA int64
+        tensor to pass as ``system_index`` to :meth:`solve` (same other
         arguments); results are bit-identical to the unplanned solve."""
         import torch
         a, _, _ = self._args(time_domain, state, params, next_h, system_index, None, options)
@@ -341,10 +343,11 @@ class Ensemble:
             stream = torch.cuda.current_stream(time_domain.device)
         lib = load_library()
         total = C.c_int64(0)
-        _check(lib.ode_ensemble_plan(self._h, C.byref(a), float(probe_fraction), None, 0,
-                                     C.byref(total), C.c_void_p(stream.cuda_stream)))
+        frac, scale = float(probe_fraction), float(probe_tolerance_scale)
+        _check(lib.ode_ensemble_plan(self._h, C.byref(a), frac, scale, None, 0, C.byref(total),
+                                     C.c_void_p(stream.cuda_stream)))
         index = torch.empty(max(total.value, 1), dtype=torch.int64, device=time_domain.device)
-        _check(lib.ode_ensemble_plan(self._h, C.byref(a), float(probe_fraction),
+        _check(lib.ode_ensemble_plan(self._h, C.byref(a), frac, scale,
                                      C.c_void_p(index.data_ptr()), index.numel(), C.byref(total),
                                      C.c_void_p(stream.cuda_stream)))
         return index[:total.value]

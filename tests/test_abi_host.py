@@ -88,7 +88,7 @@ def test_null_arguments(lib):
     r = E.TuneResult()
     assert lib.ode_ensemble_tune(None, C.byref(a), 1.0, None, C.byref(r)) == E.EINVAL
     n_pos = C.c_int64(0)
-    assert lib.ode_ensemble_plan(None, C.byref(a), 0.02, None, 0, C.byref(n_pos), None) == E.EINVAL
+    assert lib.ode_ensemble_plan(None, C.byref(a), 0.02, 1.0, None, 0, C.byref(n_pos), None) == E.EINVAL
     assert lib.ode_plan_order(None, None, 0, 1, 1, None, 0, None) == E.EINVAL
     assert lib.ode_ensemble_query(None, None) == E.EINVAL
     lib.ode_ensemble_destroy(None)  # NULL is ignored

@@ -73,3 +73,16 @@ def test_queue_plan_with_caller_index_is_bitwise_neutral():
     b = _solve(ens, pb, index)
     for k in a:
         assert np.array_equal(a[k][..., sub], b[k][..., sub], equal_nan=True), k
+
+
+def test_plan_rejects_bad_probe_arguments():
+    pb = I.duffing_rkck45_sweep().subset(np.arange(4096)).with_horizon(2 * I.TWO_PI, t_record=0.0)
+    ens = E.Ensemble(pb.model, pb.method)
+    dev = torch.device("cuda", 0)
+    td = torch.as_tensor(pb.time_domain, device=dev)
+    y = torch.as_tensor(pb.state, device=dev)
+    p = torch.as_tensor(pb.params, device=dev)
+    for kw in (dict(probe_fraction=0.0), dict(probe_fraction=1.5),
+               dict(probe_tolerance_scale=0.5), dict(probe_tolerance_scale=float("inf"))):
+        with pytest.raises(E.OdeError):
+            ens.plan(td, y, p, **kw, **pb.options)
