@@ -225,8 +225,8 @@ def main():
         print(kernel_source_hash(args.config))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the systems are independent and this build "
-              "measures the single-GPU kernel (see the design notes for how it would shard).",
+        print("bench.py runs on one GPU only: the systems are independent, so the single-GPU "
+              "kernel is what is measured (the design notes describe how it would shard).",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -42,7 +42,7 @@ enum ode_error {
   ODE_EINVAL = -1,  /* an argument is invalid (checked before any GPU work) */
   ODE_ENOMEM = -2,  /* a device or host allocation failed                  */
   ODE_EHIP = -3,    /* a HIP runtime call failed                            */
-  ODE_ENOTSUP = -4  /* valid request this build does not implement         */
+  ODE_ENOTSUP = -4  /* valid request the library does not implement       */
 };
 
 /* Built-in models (paper Sec. 2).  Parameters, in order:

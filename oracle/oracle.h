@@ -9,7 +9,7 @@
  * ODE integration package to solve large number of independent ODE systems on
  * GPUs", arXiv:1810.03931).
  *
- * Arithmetic: IEEE binary64, round to nearest, no contraction (the build uses
+ * Arithmetic: IEEE binary64, round to nearest, no contraction (compiled with
  * -ffp-contract=off), glibc libm for cos/sin/pow/sqrt.
  *
  * Layout (paper Sec. 6.1, problem pool): every per-system array is
