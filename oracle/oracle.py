@@ -12,6 +12,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# The same source with fused multiply-adds: calibrates parity bars only.
+LIB_FMA_PATH = os.path.join(HERE, "liboracle_fma.so")
 
 MODEL = {"duffing": 1, "keller_miksis": 2, "relief_valve": 3, "ballistic": 4,
          "duffing_lyapunov": 5}
@@ -51,27 +53,40 @@ class _Options(C.Structure):
 
 
 _lib = None
+_lib_fma = None
 
 
-def lib():
-    global _lib
+def lib(variant: str = "plain"):
+    """The oracle library; ``variant="fma"`` gives the contracted calibration
+    build instead."""
+    global _lib, _lib_fma
+    if variant == "fma":
+        if _lib_fma is None:
+            _lib_fma = _load(LIB_FMA_PATH)
+        return _lib_fma
+    if variant != "plain":
+        raise ValueError(f"unknown oracle variant {variant!r}")
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            from oracle import build as _b  # noqa: WPS433
-            _b.build()
-        L = C.CDLL(LIB_PATH)
-        dp, lp, ip = C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_int)
-        L.oracle_solve_batch.argtypes = [C.POINTER(_Options), C.c_longlong, C.c_longlong,
-                                         dp, dp, dp, dp, dp, ip, lp, ip, dp, lp, C.c_int]
-        L.oracle_solve_batch.restype = C.c_int
-        L.oracle_rhs.argtypes = [C.c_int, C.c_double, dp, dp, dp]
-        L.oracle_rhs.restype = C.c_int
-        L.oracle_step.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, C.c_double, dp, dp]
-        L.oracle_step.restype = C.c_int
-        L.oracle_cash_karp_tableau.argtypes = [dp, dp, dp, dp, dp]
-        L.oracle_model_dims.argtypes = [C.c_int, ip, ip]
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+def _load(path):
+    if not os.path.exists(path):
+        from oracle import build as _b  # noqa: WPS433
+        _b.build()
+    L = C.CDLL(path)
+    dp, lp, ip = C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_int)
+    L.oracle_solve_batch.argtypes = [C.POINTER(_Options), C.c_longlong, C.c_longlong,
+                                     dp, dp, dp, dp, dp, ip, lp, ip, dp, lp, C.c_int]
+    L.oracle_solve_batch.restype = C.c_int
+    L.oracle_rhs.argtypes = [C.c_int, C.c_double, dp, dp, dp]
+    L.oracle_rhs.restype = C.c_int
+    L.oracle_step.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, C.c_double, dp, dp]
+    L.oracle_step.restype = C.c_int
+    L.oracle_cash_karp_tableau.argtypes = [dp, dp, dp, dp, dp]
+    L.oracle_model_dims.argtypes = [C.c_int, ip, ip]
+    return L
 
 
 def _ptr(a, ctype):
@@ -144,13 +159,14 @@ def make_options(model, method, *, h0, rtol=1e-10, atol=1e-10, h_min=1e-12, h_ma
 
 
 def solve(model, method, time_domain, state, params, *, next_h=None, index=None, threads=0,
-          record_start=None, **opts):
+          record_start=None, variant="plain", **opts):
     """Integrate every system (or those in ``index``) in place.
 
     ``time_domain`` [2, ld], ``state`` [n_state, ld] and ``params``
     [n_param, ld] are float64 SoA arrays; ``time_domain`` and ``state`` are
     overwritten with the final time and state (and so is ``next_h`` if given).
     Returns a dict with status, counts, acc, event_counts, event_records.
+    ``variant="fma"`` runs the contracted calibration build.
     """
     o = make_options(model, method, **opts)
     if record_start is not None:
@@ -169,7 +185,7 @@ def solve(model, method, time_domain, state, params, *, next_h=None, index=None,
     counts = np.zeros((3, ld), dtype=np.int64)
     evc = np.zeros((max(o.n_events, 1), ld), dtype=np.int32)
     rec = np.full((max(o.record_cap, 1), 2, ld), np.nan)
-    rc = lib().oracle_solve_batch(
+    rc = lib(variant).oracle_solve_batch(
         C.byref(o), n, ld, _ptr(td, C.c_double), _ptr(st, C.c_double), _ptr(pr, C.c_double),
         _ptr(acc, C.c_double), _ptr(next_h, C.c_double), _ptr(status, C.c_int),
         _ptr(counts, C.c_longlong), _ptr(evc, C.c_int), _ptr(rec, C.c_double),

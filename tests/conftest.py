@@ -17,9 +17,11 @@ def oracle():
     from oracle import build as obuild
     from oracle import oracle as O
     src = os.path.join(ROOT, "oracle", "ode_oracle.c")
-    if not os.path.exists(O.LIB_PATH) or os.path.getmtime(O.LIB_PATH) < os.path.getmtime(src):
+    if any(not os.path.exists(f) or os.path.getmtime(f) < os.path.getmtime(src)
+           for f in (O.LIB_PATH, O.LIB_FMA_PATH)):
         obuild.build()
     O.lib()
+    O.lib("fma")
     return O
 
 

@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from _parity import check, compare, oracle_with_floor, run_gpu, run_oracle, take
+from _parity import check, compare, reference, run_gpu, run_oracle, take
 from paper_1810_03931_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -54,8 +54,7 @@ def test_gather_index_subset_and_invalid_entries(ode, oracle):
     chosen = rng.choice(pb.n, 700, replace=False)
     index = np.concatenate([chosen[:350], [-1, pb.n, 10**9], chosen[350:]])
     g = run_gpu(pb, index=index)
-    o, floor, fragile = oracle_with_floor(pb.subset(chosen))
-    st = compare(take(g, chosen), o, floor=floor, fragile=fragile, label="gather")
+    st = compare(take(g, chosen), reference(pb.subset(chosen)), label="gather")
     untouched = np.setdiff1d(np.arange(pb.n), chosen)
     assert np.all(g["status"][untouched] == -1)
     assert np.array_equal(g["y"][:, untouched], pb.state[:, untouched])
@@ -134,9 +133,9 @@ def test_record_overflow_and_multiple_events(ode, oracle):
         dict(component=0, level=0.5, direction=0, tolerance=1e-8),
         dict(component=1, direction=1, tolerance=1e-6, stop_after=9)])
     g = run_gpu(pb)
-    o, floor, fragile = oracle_with_floor(pb)
-    st = compare(g, o, floor=floor, fragile=fragile, label="multi-event")
-    assert np.any(o["event_counts"][0] > 3)
+    ref = reference(pb)
+    st = compare(g, ref, label="multi-event")
+    assert np.any(ref.o["event_counts"][0] > 3)
     print("[edge] multi-event", st)
 
 

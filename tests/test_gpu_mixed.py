@@ -11,7 +11,7 @@ measured against the oracle at the same tolerance, and hold it.
 import numpy as np
 import pytest
 
-from _parity import oracle_with_floor, run_gpu
+from _parity import reference, run_gpu
 from paper_1810_03931_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -34,7 +34,8 @@ def _errors(g, o):
 def test_mixed_precision_accuracy_short_horizon(ode, oracle, name):
     pb = I.with_tolerance(I.short_horizon(I.CONFIGS[name]()), TOL)
     sub = pb.subset(I.stratified_sample(pb.n, min(4999, pb.n), seed=4))
-    o, floor, fragile = oracle_with_floor(sub)
+    ref = reference(sub, calibrate=False)
+    o, floor, fragile = ref.o, ref.floor["y"], ref.fragile
     g = run_gpu(sub, precision="mixed")
     err = _errors(g, o)
     same_status = g["status"] == o["status"]

@@ -5,7 +5,7 @@ oracle, and against the same systems solved alone on the GPU (bitwise)."""
 import numpy as np
 import pytest
 
-from _parity import compare, oracle_with_floor, run_gpu, take
+from _parity import compare, reference, run_gpu, take
 from paper_1810_03931_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -34,8 +34,7 @@ def test_many_more_systems_than_resident_lanes(ode, oracle):
             a, b = g[key][..., :base_n], g[key][..., sl]
             assert np.array_equal(a, b, equal_nan=True), (k, key)
     sample = I.stratified_sample(pb.n, 1536, seed=31)
-    o, floor, fragile = oracle_with_floor(pb.subset(sample))
-    st = compare(take(g, sample), o, floor=floor, fragile=fragile, label="2^21 systems")
+    st = compare(take(g, sample), reference(pb.subset(sample)), label="2^21 systems")
     print(f"[scale] 2^21 systems: {st}", flush=True)
 
 
@@ -64,13 +63,12 @@ def test_large_leading_dimension_sparse_gather(ode, oracle):
                        y_before[:, torch.as_tensor(untouched, device=dev)])
     pick = chosen[I.stratified_sample(len(chosen), 1024, seed=34)]
     sub = base.subset(src[pick])
-    o, floor, fragile = oracle_with_floor(sub)
+    ref = reference(sub)
     g = {"y": y[:, torch.as_tensor(pick, device=dev)].cpu().numpy(),
          "t": td[0, torch.as_tensor(pick, device=dev)].cpu().numpy(),
          "status": status[pick], "counts": out["counts"].cpu().numpy()[:, pick],
          "acc": out["acc"].cpu().numpy()[:, pick],
          "event_counts": out["event_counts"].cpu().numpy()[:, pick],
          "event_records": np.zeros((0, 2, len(pick)))}
-    o = dict(o, event_records=np.zeros((0, 2, len(pick))))
-    st = compare(g, o, floor=floor, fragile=fragile, label="ld 2^22 gather")
+    st = compare(g, ref, label="ld 2^22 gather")
     print(f"[scale] ld=2^22, 50000 gathered systems: {st}", flush=True)
