@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=0.0,
                     help="override rtol = atol of the sweep (0: the sweep's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sub-records", dest="sub_records", action="store_false",
+                    help="time the headline workload only (by default the Keller-Miksis, "
+                         "relief-valve and RK4 Duffing sweeps follow, in sub-records)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--uniform", type=int, default=-1, metavar="SYSTEM",
                     help="give every system the parameters and initial state of SYSTEM, so all "
@@ -96,13 +99,13 @@ def copy_calibration(nbytes):
                       "launches": 3}), flush=True)
 
 
-def cpu_baseline(pb, target_s):
+def cpu_baseline(pb, target_s, threads=0):
     """The oracle, as it is, on a stratified sample of the same sweep over the
-    full horizon, on all host cores; accepted system-steps/s.  The sample
-    grows until one run takes at least half of target_s."""
+    full horizon, on all host cores (or ``threads``); accepted system-steps/s.
+    The sample grows until one run takes at least half of target_s."""
     from oracle import oracle as O
     from paper_1810_03931_amd import inputs as I
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = threads or int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     k = min(pb.n, 4 * threads)
     while True:
         sample = pb.subset(I.stratified_sample(pb.n, k, seed=22))
@@ -216,29 +219,17 @@ def measured_traffic(workload):
     return float(vals["bytes_per_launch"])
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.source_hash:
-        print(kernel_source_hash(args.config))
-        return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the systems are independent, so the single-GPU "
-              "kernel is what is measured (the design notes describe how it would shard).",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_1810_03931_amd import ensemble as E
-    from paper_1810_03931_amd import inputs as I
+# Further single-GPU workloads timed in the default run, each in a sub-record of
+# the same JSON line: (name, timed steps, warmup steps).
+SUB_WORKLOADS = (("keller_miksis", 2, 1), ("relief_valve", 3, 1), ("duffing_rk4", 10, 2))
 
-    if not os.path.exists(E.LIB_PATH):
-        from paper_1810_03931_amd import build
-        build.build()
+
+def bench_workload(torch, E, name, args, steps, warmup):
+    """Time ``steps`` full solves of workload ``name`` after ``warmup``
+    untimed ones; return the measurements (the JSON record without the CPU
+    baseline)."""
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    pb = I.CONFIGS[args.config]()
+    pb = I.CONFIGS[name]()
     if args.tol > 0:
         pb = I.with_tolerance(pb, args.tol)
     if args.uniform >= 0:
@@ -316,15 +307,17 @@ def main():
         waves_per_simd = pb.n / (64.0 * 4 * max(info0["compute_units"], 1))
         if pb.n <= info0["resident_systems"] and waves_per_simd >= 2:
             plan_frac = 0.04
-    for _ in range(args.warmup):
+    print(f"[bench] {name}: {warmup} warmup + {steps} timed steps", file=sys.stderr, flush=True)
+    for _ in range(warmup):
         step()
+        torch.cuda.synchronize()
     plan_ms.clear()
     torch.cuda.synchronize()
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
     kernel_events, wall = [], []
     s0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         w0 = time.perf_counter()
         kernel_events.append(step())
         torch.cuda.synchronize()
@@ -343,7 +336,7 @@ def main():
         counts = counts * n_seg
     status = np.bincount(out["status"].cpu().numpy() & 0xFF, minlength=6)
     accepted, attempts = int(counts[0]), int(counts.sum())
-    ms_per_step = total_ms / args.steps
+    ms_per_step = total_ms / steps
     value = accepted / (ms_per_step / 1e3)
 
     # the repeated-horizon workload runs the RK4 Duffing kernel of duffing_rk4
@@ -359,19 +352,16 @@ def main():
     traffic = measured_traffic(pb.name) if (args.uniform < 0 and args.precision == "fp64"
                                             and args.tol <= 0) else None
     info = ens.info()
-    line = {
-        "metric": METRIC, "value": value, "unit": "system-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 stages / f64 state",
-        "data": "synthetic (seeded parameter sweep)",
+    rec = {
+        "value": value, "unit": "system-steps/s", "steps": steps, "warmup": warmup,
+        "ms_per_step": ms_per_step,
         "config": {"workload": pb.name + ("/uniform" if args.uniform >= 0 else ""),
                    "systems": pb.n, "equation": pb.model, "method": pb.method,
                    "horizon": float(pb.time_domain[1, 0]) * (n_seg if segments else 1),
                    "t_record": pb.options.get("t_record"),
                    "rtol": pb.options.get("rtol"), "precision": args.precision,
                    "block_size": info["block_size"], "blocks_per_cu": info["blocks_per_cu"],
-                   "resident_systems": info["resident_systems"], "tuned": tuned is not None,
+                   "resident_systems": info["resident_systems"], "tuned": tuned,
                    "queue_plan": ({"probe_fraction": plan_frac,
                                    "probe_tolerance_scale": args.plan_tol_scale,
                                    "plan_ms": float(np.mean(plan_ms)) if plan_ms else None,
@@ -387,7 +377,6 @@ def main():
         "p50_ms": float(np.percentile(np.array(wall) * 1e3, 50)),
         "p99_ms": float(np.percentile(np.array(wall) * 1e3, 99)),
         "kernel_ms": float(kernel_ms.mean()),
-        "device": device_facts(torch, info),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic,
@@ -396,8 +385,54 @@ def main():
                      "flops_per_attempt": flops_attempt, "flops_per_attempt_source": flops_src,
                      "attempts_per_launch": attempts},
     }
+    return rec, pb, info
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.source_hash:
+        print(kernel_source_hash(args.config))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the systems are independent, so the single-GPU "
+              "kernel is what is measured (the design notes describe how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1810_03931_amd import ensemble as E
+
+    if not os.path.exists(E.LIB_PATH):
+        from paper_1810_03931_amd import build
+        build.build()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    rec, pb, info = bench_workload(torch, E, args.config, args, args.steps, args.warmup)
+    line = {"metric": METRIC, "value": rec["value"], "unit": rec["unit"], "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.precision == "fp64" else "f32 stages / f64 state",
+            "data": "synthetic (seeded parameter sweep)"}
+    line.update({k: v for k, v in rec.items() if k not in line})
+    line["device"] = device_facts(torch, info)
+    if args.sub_records and args.config == "duffing_rkck45" and args.uniform < 0:
+        subs = {}
+        for name, k, w in SUB_WORKLOADS:
+            r, _, _ = bench_workload(torch, E, name, args, k, w)
+            subs[name] = {key: r[key] for key in ("value", "unit", "steps", "warmup",
+                                                  "ms_per_step", "kernel_ms",
+                                                  "attempted_steps_per_s", "attempts_per_system",
+                                                  "status_counts", "config")}
+            subs[name]["roofline"] = {key: r["roofline"][key] for key in (
+                "bound", "achieved", "peak", "unit", "frac", "traffic", "flops_per_attempt",
+                "flops_per_attempt_source", "attempts_per_launch")}
+            torch.cuda.empty_cache()
+        line["workloads"] = subs
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
+        line["cpu_baseline_1core"] = cpu_baseline(pb, args.cpu_seconds, threads=1)
     print(json.dumps(line), flush=True)
 
 

@@ -86,12 +86,15 @@ int combo_index(int nev, int nacc) {
 
 }  // namespace
 
-// Arguments a cached repeated-horizon graph was recorded for.
+// Arguments and launch shape a cached repeated-horizon graph was recorded
+// for (a change of block size or residency, e.g. by the autotuner, records a
+// new graph).
 struct SegmentsKey {
   ode_solve_args args;
   int32_t n_segments, first_snapshot;
   double segment;
   double *snapshots;
+  int32_t block, cap;
 };
 
 struct ode_ensemble {
@@ -441,6 +444,8 @@ int ode_ensemble_solve_segments(ode_ensemble *e, const ode_solve_args *a, int32_
   key.first_snapshot = first_snapshot;
   key.segment = segment;
   key.snapshots = snapshots;
+  key.block = e->block;
+  key.cap = e->cap;
   // the event and accessory arrays beyond the counts in use do not matter
   for (int j = a->n_events; j < ODE_MAX_EVENTS; ++j) std::memset(&key.args.events[j], 0, sizeof(ode_event_spec));
   for (int k = a->n_accessories; k < ODE_MAX_ACCESSORIES; ++k)

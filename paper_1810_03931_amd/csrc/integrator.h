@@ -34,9 +34,11 @@ struct AccCtl {
 };
 constexpr int32_t kAccMax = 1, kAccMin = 2, kAccLogReset = 3;
 
-// Solver-wide constants.  Passed by value: they live in the kernel-argument
-// segment and every wave reads them into scalar registers, so the per-lane
-// vector registers stay free for the integration state.
+// Solver-wide constants.  Passed by value in the kernel-argument segment.
+// The kernel copies the ones every attempt reads into vector registers once
+// per launch (scalar loads inside the attempt loop would stall a wave that
+// runs alone); the rarely used fields are read from the argument segment
+// where they are needed.
 struct Control {
   double rtol[kMaxState], atol[kMaxState];
   double h0, h_min, h_max, grow, shrink, t_record;
