@@ -103,7 +103,8 @@ enum ode_lane_status {
                                     an event zone (Sec. 4, configuration d)    */
   ODE_LANE_FAIL_NAN = 3,         /* NaN with the minimum step (Sec. 6.5)        */
   ODE_LANE_MAX_STEPS = 4,        /* max_steps attempts used                     */
-  ODE_LANE_BAD_INPUT = 5         /* non-finite t0 or t1                         */
+  ODE_LANE_BAD_INPUT = 5         /* non-finite t0 or t1, or invalid per-system
+                                    tolerances                                */
 };
 #define ODE_LANE_FLAG_SECANT_CAP 0x100 /* an event location hit its 50-iteration cap */
 
@@ -171,6 +172,17 @@ typedef struct {
                                  different windows can share one launch);
                                  NaN: the window never opens; NULL: t_record
                                  for every system                          */
+  const double *tolerances;   /* [2*n_state][ld] per-system tolerances
+                                 (RKCK45), replacing rtol and atol: rows
+                                 0..n_state-1 relative, n_state..2*n_state-1
+                                 absolute, per component (so requests with
+                                 different tolerances can share one launch).
+                                 A system whose entries are not finite and
+                                 >= 0 with a positive rtol+atol sum per
+                                 component gets ODE_LANE_BAD_INPUT.  NULL:
+                                 rtol and atol for every system.  Not part
+                                 of the paper, whose tolerances are shared by
+                                 all systems of a solver object (Sec. 6.5)  */
   double rtol[ODE_MAX_STATE]; /* per component, >= 0, rtol+atol > 0 (RKCK45) */
   double atol[ODE_MAX_STATE];
   double h0;                  /* initial step (RKCK45) or fixed step (RK4), > 0 */

@@ -321,6 +321,20 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
   oracle_model_dims(o->model, NULL, &np);
   for (int j = 0; j < np; ++j) p[j] = params[(long long)j * ld + s];
 
+  /* Tolerances (paper Sec. 6.5).  A serving extension, not in the paper:
+   * each system may carry its own, so that requests with different
+   * tolerances share one solve; each system is still the paper's problem. */
+  double rtol[OR_MAX_STATE], atol[OR_MAX_STATE];
+  int tol_ok = 1;
+  for (int i = 0; i < n; ++i) {
+    rtol[i] = o->tolerances ? o->tolerances[(long long)i * ld + s] : o->rtol[i];
+    atol[i] = o->tolerances ? o->tolerances[(long long)(n + i) * ld + s] : o->atol[i];
+    if (o->tolerances && o->method == OR_RKCK45 &&
+        !(rtol[i] >= 0.0 && atol[i] >= 0.0 && rtol[i] + atol[i] > 0.0 &&
+          isfinite(rtol[i] + atol[i])))
+      tol_ok = 0;
+  }
+
   double t0 = time_domain[s], t1 = time_domain[ld + s];
   double t = t0;
   /* start of this system's recording window */
@@ -366,7 +380,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
   double accv[OR_MAX_ACC], acct[OR_MAX_ACC];
   int window_open = 0;
 
-  if (!isfinite(t0) || !isfinite(t1)) status = OR_BAD_INPUT;
+  if (!isfinite(t0) || !isfinite(t1) || !tol_ok) status = OR_BAD_INPUT;
 
   /* Poincare sections (paper Sec. 2.1: t_n = n*T).  READING R29: n counts
    * from the origin of time, not from t0, so a solve split in two visits the
@@ -435,7 +449,7 @@ static void solve_one(const or_options *o, int n, long long s, long long ld, dou
       double E = 0.0;
       for (int i = 0; i < n; ++i) {
         if (isnan(yn[i])) has_nan = 1;
-        double sc = o->atol[i] + o->rtol[i] * fmax(fabs(y[i]), fabs(yn[i]));
+        double sc = atol[i] + rtol[i] * fmax(fabs(y[i]), fabs(yn[i]));
         double r = fabs(err[i]) / sc;
         if (isnan(r)) has_nan = 1;
         if (r > E) E = r;

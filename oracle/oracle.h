@@ -91,6 +91,9 @@ typedef struct {
                           * n integer) are forced step boundaries; 0: none */
   const double *record_start; /* [ld] per-system window start replacing
                                * t_record; NULL: t_record for every system */
+  const double *tolerances;   /* [2*n_state][ld] per-system relative (rows
+                               * 0..n_state-1) and absolute tolerances
+                               * replacing rtol/atol; NULL: rtol/atol      */
   int max_equilibrium_steps; /* 0 disables the equilibrium stop            */
   long long max_steps;       /* attempt budget per system                  */
   int n_events;

@@ -46,6 +46,7 @@ class _Options(C.Structure):
         ("h0", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
         ("grow", C.c_double), ("shrink", C.c_double), ("t_record", C.c_double),
         ("section_period", C.c_double), ("record_start", C.POINTER(C.c_double)),
+        ("tolerances", C.POINTER(C.c_double)),
         ("max_equilibrium_steps", C.c_int), ("max_steps", C.c_longlong),
         ("n_events", C.c_int), ("n_acc", C.c_int), ("record_cap", C.c_int),
         ("ev", _Event * 4), ("acc", _Acc * 4),
@@ -159,7 +160,7 @@ def make_options(model, method, *, h0, rtol=1e-10, atol=1e-10, h_min=1e-12, h_ma
 
 
 def solve(model, method, time_domain, state, params, *, next_h=None, index=None, threads=0,
-          record_start=None, variant="plain", **opts):
+          record_start=None, tolerances=None, variant="plain", **opts):
     """Integrate every system (or those in ``index``) in place.
 
     ``time_domain`` [2, ld], ``state`` [n_state, ld] and ``params``
@@ -173,6 +174,10 @@ def solve(model, method, time_domain, state, params, *, next_h=None, index=None,
         record_start = np.ascontiguousarray(record_start, dtype=np.float64)
         assert record_start.shape == (time_domain.shape[1],)
         o.record_start = _ptr(record_start, C.c_double)
+    if tolerances is not None:
+        tolerances = np.ascontiguousarray(tolerances, dtype=np.float64)
+        assert tolerances.shape == (2 * DIMS[model][0], time_domain.shape[1])
+        o.tolerances = _ptr(tolerances, C.c_double)
     td = np.ascontiguousarray(time_domain, dtype=np.float64)
     st = np.ascontiguousarray(state, dtype=np.float64)
     pr = np.ascontiguousarray(params, dtype=np.float64)

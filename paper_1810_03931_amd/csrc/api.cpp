@@ -362,6 +362,7 @@ static int prepare_launch(ode_ensemble *e, const ode_solve_args *a, Params &prm,
   arr.rec = a->event_records;
   arr.index = a->system_index;
   arr.t_rec = a->record_start;
+  arr.tol = a->tolerances;
   arr.n = a->n_systems;
   arr.ld = a->ld;
   arr.queue = e->queue;

@@ -64,6 +64,7 @@ struct Arrays {
   double *rec;
   const int64_t *index;
   const double *t_rec;  // per-system window start, or nullptr (Control::t_record)
+  const double *tol;    // per-system [2*n_state][ld] rtol, atol, or nullptr
   int64_t n, ld;
   unsigned long long *queue;  // [0] next queue position, [1] finished waves
   uint32_t total_waves;

@@ -312,6 +312,7 @@ __device__ __forceinline__ Arrays arrays_of(ParamsRef q) {
   a.rec = q->a.rec;
   a.index = q->a.index;
   a.t_rec = q->a.t_rec;
+  a.tol = q->a.tol;
   a.n = q->a.n;
   a.ld = q->a.ld;
   a.queue = q->a.queue;
@@ -487,7 +488,8 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     active = false;
   };
 
-  const HotControl<N, EV, AC> hc = hot_control<N, EV, AC>(c);
+  // per lane: a system's own tolerances replace the launch's at refill
+  HotControl<N, EV, AC> hc = hot_control<N, EV, AC>(c);
 
   for (;;) {
     // ---- refill idle lanes from the queue (all 64 lanes are converged here) ----
@@ -537,6 +539,17 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             if constexpr (PREC == kPrecMixed) {
               M::prepare32(p, pf);
             }
+            bool tol_ok = true;
+            if (METHOD == kMethodRKCK45 && a.tol) {
+#pragma unroll
+              for (int i = 0; i < N; ++i) {
+                const double rt = a.tol[i * ld + s], at = a.tol[(N + i) * ld + s];
+                tol_ok = tol_ok && rt >= 0.0 && at >= 0.0 && rt + at > 0.0 &&
+                         rt + at < __builtin_huge_val();
+                hc.rtol[i] = rt;
+                hc.atol[i] = at;
+              }
+            }
             attempts = n_acc = n_rej = flags = 0;
             status = kRunning;
             locating = false;
@@ -565,7 +578,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             }
             window_open = false;
             sec_n = 0.0;
-            if (!isfinite(t) || !isfinite(t1)) {
+            if (!isfinite(t) || !isfinite(t1) || !tol_ok) {
               status = kBadInput;
             } else {
               // Poincare sections n*T count from time zero; the first one is

@@ -42,7 +42,7 @@ struct KellerMiksis {
                                              const double (&F)[NF], double (&f)[NS]) {
     const double y1 = y[0], y2 = y[1];
     const double rx = 1.0 / y1;
-    const double gas = pow(rx, C[10]);
+    const double gas = pow_pos(rx, C[10]);
     const double u = fma(C[9], y2, 1.0);                     // 1 + C9*y2
     const double forcing_p = fma(C[5], F[0], C[6] * F[2]);   // C5 sin + C6 sin
     const double forcing_d = fma(C[7], F[1], C[8] * F[3]);   // C7 cos + C8 cos

@@ -66,7 +66,7 @@ class SolveArgs(C.Structure):
         ("time_domain", C.c_void_p), ("state", C.c_void_p), ("params", C.c_void_p),
         ("accessories", C.c_void_p), ("next_h", C.c_void_p), ("status", C.c_void_p),
         ("counts", C.c_void_p), ("event_counts", C.c_void_p), ("event_records", C.c_void_p),
-        ("system_index", C.c_void_p), ("record_start", C.c_void_p),
+        ("system_index", C.c_void_p), ("record_start", C.c_void_p), ("tolerances", C.c_void_p),
         ("rtol", C.c_double * MAX_STATE), ("atol", C.c_double * MAX_STATE),
         ("h0", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
         ("grow", C.c_double), ("shrink", C.c_double), ("t_record", C.c_double),
@@ -260,6 +260,7 @@ class Ensemble:
         import torch
         options = dict(options)
         record_start = options.pop("record_start", None)
+        tolerances = options.pop("tolerances", None)
         ld = int(time_domain.shape[-1])
         events = list(options.get("events", ()))
         accs = list(options.get("accessories", ()))
@@ -293,6 +294,8 @@ class Ensemble:
             a.system_index = system_index.data_ptr() if n else None
         if record_start is not None:
             a.record_start = _ptr(record_start, torch.float64, 1, ld, "record_start")
+        if tolerances is not None:
+            a.tolerances = _ptr(tolerances, torch.float64, 2 * self.n_state, ld, "tolerances")
         fill_args(a, self.n_state, **options)
         return a, out, len(accs)
 

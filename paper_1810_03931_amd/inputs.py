@@ -316,12 +316,13 @@ def _served_base(name: str) -> Problem:
     return keller_miksis_sweep(1 << 16)
 
 
-def served_mix(n_requests: int = 600, *, seed: int = 0, tol: float = 1e-7,
-               sizes=(256, 65536), periods=(8, 256)) -> list[Request]:
+def served_mix(n_requests: int = 600, *, seed: int = 0, tol=(1e-7, 1e-6),
+               sizes=(256, 65536), periods=(64, 2048)) -> list[Request]:
     """Requests: model uniform over the three sweeps; size log-uniform over
     ``sizes`` systems (a contiguous slice at a uniform offset); horizon
     log-uniform over ``periods`` forcing periods, the last 1/16 (at least one)
-    recorded; adaptive requests at rtol = atol = ``tol``."""
+    recorded; adaptive requests at rtol = atol = ``tol``, or, for a range
+    (lo, hi), at a tolerance log-uniform over it drawn per request."""
     g = np.random.default_rng(SEED_BASE + 100 + seed)
     bases = {name: _served_base(name) for name in SERVED_MODELS}
     out = []
@@ -335,7 +336,11 @@ def served_mix(n_requests: int = 600, *, seed: int = 0, tol: float = 1e-7,
         T = 1.0 if base.model == "keller_miksis" else TWO_PI
         pb = base.subset(np.arange(a, a + m))
         pb = pb.with_horizon(P * T, t_record=(P - max(1, P // 16)) * T)
-        pb = with_tolerance(pb, tol)
+        if np.ndim(tol):
+            t = float(10.0 ** g.uniform(math.log10(tol[0]), math.log10(tol[1])))
+        else:
+            t = float(tol)
+        pb = with_tolerance(pb, t)
         pb.name = f"{name}#{rid}"
         out.append(Request(rid, pb, P))
     return out

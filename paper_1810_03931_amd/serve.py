@@ -9,9 +9,11 @@ request's inputs to the device on the slot's stream and enqueues its solve.
 It polls completion events, copies the results back, releases the memory and
 admits the next requests.
 
-Waiting requests that can share a launch (same model, method and options;
-horizons within a factor of two) are batched into one solve: their systems
-sit side by side, each with its own window start (``record_start``).
+Waiting requests that can share a launch (same model, method, events and
+accessories; horizons within a factor of two) are batched into one solve:
+their systems sit side by side, each with its own window start
+(``record_start``) and its own tolerances (``tolerances``), so requests with
+different windows and tolerances run in one persistent kernel.
 Launches on different slots run concurrently.  When one launch's workgroups
 retire, the freed compute units take workgroups of the others, so requests
 arriving while others run start right away, up to the slot and memory
@@ -45,7 +47,8 @@ def request_bytes(pb: I.Problem) -> int:
     evs = pb.options.get("events", ())
     cap = pb.options.get("record_cap", 0) if any(e.get("record_component", -1) >= 0
                                                  for e in evs) else 0
-    rows = 2 + pb.state.shape[0] + pb.params.shape[0] + 2 * n_acc + 2 * cap
+    ns = pb.state.shape[0]
+    rows = 2 + ns + pb.params.shape[0] + 2 * n_acc + 2 * cap + 1 + 2 * ns
     return n * (8 * rows + 4 + 3 * 8 + 4 * len(evs))
 
 
@@ -63,11 +66,24 @@ class Result:
         return self.done - self.arrival
 
 
+# Options that become per-system arrays of a batched launch.
+PER_SYSTEM = ("t_record", "rtol", "atol")
+
+
 def _batch_key(pb: I.Problem) -> str:
     """Requests with equal keys can share one launch: same model, method and
-    options except the window start, which becomes per system."""
-    opts = {k: v for k, v in pb.options.items() if k != "t_record"}
+    options except the window start and the tolerances, which become per
+    system."""
+    opts = {k: v for k, v in pb.options.items() if k not in PER_SYSTEM}
     return json.dumps([pb.model, pb.method, opts], sort_keys=True, default=str)
+
+
+def _tolerances(pb: I.Problem) -> np.ndarray:
+    """[2*n_state, n] relative then absolute tolerance of every system."""
+    ns = pb.state.shape[0]
+    rt = np.broadcast_to(np.asarray(pb.options.get("rtol", 1e-10), dtype=np.float64), (ns,))
+    at = np.broadcast_to(np.asarray(pb.options.get("atol", 1e-10), dtype=np.float64), (ns,))
+    return np.repeat(np.concatenate([rt, at])[:, None], pb.n, axis=1)
 
 
 class _Slot:
@@ -98,13 +114,16 @@ class _Slot:
         y = cat(lambda pb: pb.state)
         p = cat(lambda pb: pb.params)
         rec = cat(lambda pb: np.full(pb.n, pb.options.get("t_record", -np.inf)))
-        opts = {k: v for k, v in first.options.items() if k != "t_record"}
+        tol = cat(_tolerances)
+        opts = {k: v for k, v in first.options.items() if k not in PER_SYSTEM}
         with torch.cuda.stream(self.stream):
-            hosts = [torch.from_numpy(a).pin_memory() for a in (td, y, p, rec)]
+            hosts = [torch.from_numpy(a).pin_memory() for a in (td, y, p, rec, tol)]
             dev = [h.to(self.device, non_blocking=True) for h in hosts]
             ens = self.handle(first.model, first.method)
-            out = ens.solve(dev[0], dev[1], dev[2], record_start=dev[3], stream=self.stream,
-                            **opts)
+            per_system = {"record_start": dev[3]}
+            if first.method == "rkck45":
+                per_system["tolerances"] = dev[4]
+            out = ens.solve(dev[0], dev[1], dev[2], stream=self.stream, **per_system, **opts)
             res = {"t": dev[0][0], "y": dev[1], "status": out["status"], "counts": out["counts"]}
             if out.get("acc") is not None:
                 res["acc"] = out["acc"]
@@ -220,14 +239,20 @@ def summarize(results: list, label: str) -> dict:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="served mix: Poisson arrivals of sweep requests")
     ap.add_argument("--requests", type=int, default=600)
-    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--tol", type=float, nargs=2, default=[1e-7, 1e-6], metavar=("LO", "HI"),
+                    help="per-request tolerance, log-uniform over [LO, HI]")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8],
                     help="offered load as fractions of the measured saturation rate")
     ap.add_argument("--precision", nargs="+", default=["fp64", "mixed"])
-    ap.add_argument("--max-periods", type=int, default=256)
+    ap.add_argument("--periods", type=int, nargs=2, default=[64, 2048], metavar=("LO", "HI"),
+                    help="per-request horizon in forcing periods, log-uniform over [LO, HI]")
     args = ap.parse_args(argv)
-    reqs = I.served_mix(args.requests, tol=args.tol, periods=(8, args.max_periods))
+    reqs = I.served_mix(args.requests, tol=tuple(args.tol), periods=tuple(args.periods))
+    print(json.dumps({"served_mix": {"requests": len(reqs), "tolerance": args.tol,
+                                     "periods": args.periods, "sizes": [256, 65536],
+                                     "models": list(I.SERVED_MODELS), "slots": args.slots}}),
+          flush=True)
     lines = []
     for prec in args.precision:
         srv = Server(precision=prec, slots=args.slots)

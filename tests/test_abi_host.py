@@ -105,7 +105,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(ode_solve_args), sizeof(ode_event_spec),
          sizeof(ode_accessory_spec), sizeof(ode_ensemble_desc), sizeof(ode_ensemble_info),
          sizeof(ode_tune_result));
-  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(ode_solve_args, rtol), offsetof(ode_solve_args, h0),
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", offsetof(ode_solve_args, tolerances),
+         offsetof(ode_solve_args, rtol), offsetof(ode_solve_args, h0),
          offsetof(ode_solve_args, section_period), offsetof(ode_solve_args, max_steps),
          offsetof(ode_solve_args, events), offsetof(ode_solve_args, accessory_specs));
   return 0;
@@ -119,7 +120,7 @@ int main(void) {
     assert sizes == [C.sizeof(E.SolveArgs), C.sizeof(E.EventSpec), C.sizeof(E.AccessorySpec),
                      C.sizeof(E.Desc), C.sizeof(E.Info), C.sizeof(E.TuneResult)]
     S = E.SolveArgs
-    assert offs == [S.rtol.offset, S.h0.offset, S.section_period.offset, S.max_steps.offset,
+    assert offs == [S.tolerances.offset, S.rtol.offset, S.h0.offset, S.section_period.offset, S.max_steps.offset,
                     S.events.offset, S.accessory_specs.offset]
 
 
