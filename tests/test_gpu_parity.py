@@ -92,7 +92,7 @@ def test_full_horizon_full_size_sampled(ode, oracle, name):
         assert np.all(gs["acc"][1::2][:, done] <= sub.time_domain[1][done])
         assert np.all(gs["acc"][0, done] >= gs["acc"][2, done])
     r2, restarted = restart_reference(sub, ref, g1s)
-    st = compare_window(g2s, r2, ref, label=f"{name}/long")
+    st = compare_window(g2s, r2, ref, label=f"{name}/long", pb=sub)
     st["restarted"] = int(np.sum(restarted & ref.stable))
     _report(f"{name} full-horizon sample={len(sample)}", st)
     # the screen keeps a fixed share of each sweep (set from the oracle alone)
