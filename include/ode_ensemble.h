@@ -246,6 +246,28 @@ int ode_ensemble_create(const ode_ensemble_desc *desc, ode_ensemble **out);
  * the same time; separate handles may run concurrently. */
 int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *args, void *hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * integration as ode_ensemble_create(desc) + ode_ensemble_solve(args) +
+ * ode_ensemble_destroy, with the same kernels, arguments, results and errors,
+ * but without a handle: the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  The caller passes the inputs and outputs as
+ * for ode_ensemble_solve.
+ * The work-queue counters live in a static device array of the library (two
+ * 64-bit counters, 16 bytes, whatever the problem size; each GPU the library
+ * runs on holds its own copy until the process ends).  Its device address is
+ * looked up on the first call on each device, with that device current.  Each
+ * call clears the counters with a small kernel on hip_stream before the
+ * integrator launch (no memset node, so the call can be captured into a graph
+ * and replayed).  Every call on one GPU shares that array: calls whose work
+ * overlaps on one GPU (e.g. on two streams) race on it and must not be made;
+ * calls on one stream are ordered and safe.  Problem sizes are limited as for
+ * ode_ensemble_solve (ld <= 2^40).
+ * Errors: ODE_EINVAL (as create + solve), ODE_ENOTSUP (device index >= 64),
+ * ODE_EHIP. */
+int ode_ensemble_solve_noalloc(const ode_ensemble_desc *desc, const ode_solve_args *args,
+                               void *hip_stream);
+
 /* Repeated horizons, captured once as a HIP graph.  This is the paper's
  * Sec. 7 workflow: a sweep advanced one excitation period per solve call,
  * each end point starting the next call, with the points of the last calls

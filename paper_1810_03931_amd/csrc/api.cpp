@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -383,6 +384,91 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   if (rc != ODE_OK) return rc;
   hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid,
                                      e->block, static_cast<hipStream_t>(hip_stream));
+  if (err != hipSuccess) return hip_fail(err, "integrator launch");
+  return ODE_OK;
+}
+
+// ---- Solves that allocate nothing (ode_ensemble_solve_noalloc) ----
+//
+// The only device memory a solve needs beyond the caller's arrays is the
+// work-queue counter pair.  For callers that cannot allocate, it lives in
+// this file-scope array: one copy per GPU, loaded with the code object and
+// held until the process ends.  Host code never passes `scratch` itself to a
+// kernel (its name is a host-side stand-in there); it uses the device address
+// that hipGetSymbolAddress returns, looked up once per device with that
+// device current.
+namespace {
+
+constexpr int kScratchWords = 2;  // [0] next queue position, [1] finished waves
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+unsigned long long *g_scratch_ptr[kMaxDevices];  // device address per device, or null
+
+int scratch_of_device(int dev, unsigned long long **out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(ODE_ENOTSUP, "device %d: at most %d devices are supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (err != hipSuccess) return hip_fail(err, "hipGetSymbolAddress of the scratch counters");
+    g_scratch_ptr[dev] = static_cast<unsigned long long *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return ODE_OK;
+}
+
+// Zeroes the counters on the stream before a launch (a kernel, not
+// hipMemsetAsync, so the call can be recorded into a graph and replayed).
+__global__ void clear_scratch(unsigned long long *words, int n) {
+  if ((int)threadIdx.x < n) words[threadIdx.x] = 0ull;
+}
+
+}  // namespace
+
+extern "C" int ode_ensemble_solve_noalloc(const ode_ensemble_desc *desc, const ode_solve_args *a,
+                                          void *hip_stream) {
+  if (!desc || !a) return fail(ODE_EINVAL, "NULL descriptor or arguments");
+  ode_ensemble e;
+  std::memset(&e, 0, sizeof e);
+  if (!model_dims(desc->model, &e.n_state, &e.n_param))
+    return fail(ODE_EINVAL, "unknown model %d", desc->model);
+  if (desc->method != ODE_RKCK45 && desc->method != ODE_RK4)
+    return fail(ODE_EINVAL, "unknown method %d", desc->method);
+  if (desc->precision != ODE_FP64 && desc->precision != ODE_FP32_STAGES)
+    return fail(ODE_EINVAL, "unknown precision %d", desc->precision);
+  const int block = desc->block_size == 0 ? kDefaultBlock : desc->block_size;
+  if (block < 64 || block > kMaxBlock || block % 64 != 0)
+    return fail(ODE_EINVAL, "block_size %d must be a multiple of 64 in [64, %d]",
+                desc->block_size, kMaxBlock);
+  if (desc->blocks_per_cu < 0) return fail(ODE_EINVAL, "blocks_per_cu must be >= 0");
+  e.model = desc->model;
+  e.method = desc->method;
+  e.precision = desc->precision;
+  e.block = block;
+  e.cap = desc->blocks_per_cu;
+  int rc = validate(&e, a);
+  if (rc != ODE_OK) return rc;
+  if (a->n_systems == 0) return ODE_OK;
+
+  hipError_t err = hipGetDevice(&e.device);
+  if (err != hipSuccess) return hip_fail(err, "hipGetDevice");
+  err = hipDeviceGetAttribute(&e.compute_units, hipDeviceAttributeMultiprocessorCount, e.device);
+  if (err != hipSuccess) return hip_fail(err, "hipDeviceGetAttribute");
+  rc = scratch_of_device(e.device, &e.queue);
+  if (rc != ODE_OK) return rc;
+
+  Params prm;
+  int nev = 0, nacc = 0, grid = 0;
+  rc = prepare_launch(&e, a, prm, nev, nacc, grid);
+  if (rc != ODE_OK) return rc;
+  const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(clear_scratch, dim3(1), dim3(64), 0, st, e.queue, kScratchWords);
+  err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(err, "clearing the scratch counters");
+  err = launch_integrator(e.model, e.method, e.precision, nev, nacc, prm, grid, e.block, st);
   if (err != hipSuccess) return hip_fail(err, "integrator launch");
   return ODE_OK;
 }

@@ -84,8 +84,8 @@ class Info(C.Structure):
 
 
 EXPORTS = ("ode_ensemble_model_dims", "ode_ensemble_create", "ode_ensemble_solve",
-           "ode_ensemble_solve_segments", "ode_ensemble_tune", "ode_ensemble_plan",
-           "ode_plan_order", "ode_ensemble_query", "ode_ensemble_destroy",
+           "ode_ensemble_solve_noalloc", "ode_ensemble_solve_segments", "ode_ensemble_tune",
+           "ode_ensemble_plan", "ode_plan_order", "ode_ensemble_query", "ode_ensemble_destroy",
            "ode_ensemble_last_error")
 
 _lib = None
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH):
     L.ode_ensemble_create.restype = C.c_int
     L.ode_ensemble_solve.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_void_p]
     L.ode_ensemble_solve.restype = C.c_int
+    L.ode_ensemble_solve_noalloc.argtypes = [C.POINTER(Desc), C.POINTER(SolveArgs), C.c_void_p]
+    L.ode_ensemble_solve_noalloc.restype = C.c_int
     L.ode_ensemble_solve_segments.argtypes = [C.c_void_p, C.POINTER(SolveArgs), C.c_int32,
                                               C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
     L.ode_ensemble_solve_segments.restype = C.c_int
@@ -208,36 +210,17 @@ def fill_args(args: SolveArgs, n_state: int, *, h0: float, rtol=1e-10, atol=1e-1
         args.accessory_specs[k].component = comp
 
 
-class Ensemble:
-    """A solver handle for one (model, method, precision) on the current
-    device (paper Sec. 6.2)."""
+class _Solver:
+    """What a solve is for: (model, method, precision) and the launch shape;
+    marshals the arguments of one solve."""
 
     def __init__(self, model: str, method: str, precision: str = "fp64", block_size: int = 0,
                  blocks_per_cu: int = 0):
-        L = load_library()
+        load_library()
         self.model, self.method = model, method
         self.n_state, self.n_param = model_dims(model)
-        d = Desc(MODEL[model], METHOD[method], PRECISION.get(precision, -1), block_size,
-                 blocks_per_cu)
-        h = C.c_void_p()
-        _check(L.ode_ensemble_create(C.byref(d), C.byref(h)))
-        self._h = h
-
-    def close(self):
-        if getattr(self, "_h", None):
-            load_library().ode_ensemble_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-    def info(self) -> dict:
-        i = Info()
-        _check(load_library().ode_ensemble_query(self._h, C.byref(i)))
-        return {f: getattr(i, f) for f, _ in Info._fields_}
+        self._desc = Desc(MODEL[model], METHOD[method], PRECISION.get(precision, -1), block_size,
+                          blocks_per_cu)
 
     def outputs(self, ld: int, *, n_accessories: int = 0, n_events: int = 0, record_cap: int = 0,
                 device=None) -> dict:
@@ -298,6 +281,34 @@ class Ensemble:
             a.tolerances = _ptr(tolerances, torch.float64, 2 * self.n_state, ld, "tolerances")
         fill_args(a, self.n_state, **options)
         return a, out, len(accs)
+
+
+class Ensemble(_Solver):
+    """A solver handle for one (model, method, precision) on the current
+    device (paper Sec. 6.2)."""
+
+    def __init__(self, model: str, method: str, precision: str = "fp64", block_size: int = 0,
+                 blocks_per_cu: int = 0):
+        super().__init__(model, method, precision, block_size, blocks_per_cu)
+        h = C.c_void_p()
+        _check(load_library().ode_ensemble_create(C.byref(self._desc), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ode_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = Info()
+        _check(load_library().ode_ensemble_query(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
 
     def solve(self, time_domain, state, params, *, next_h=None, system_index=None, out=None,
               stream=None, **options: Any) -> dict:
@@ -385,6 +396,26 @@ class Ensemble:
             self._h, C.byref(a), int(n_segments), float(segment), int(first_snapshot), snap_ptr,
             C.c_void_p(stream.cuda_stream)))
         out["snapshots"] = snapshots
+        return out
+
+
+class NoAllocSolver(_Solver):
+    """Solves through ``ode_ensemble_solve_noalloc``: no handle and no device
+    allocation in the library (the work-queue counters are the library's
+    static device array).  For callers that cannot allocate, e.g. code under
+    HIP graph capture; pass preallocated outputs (``outputs``) to allocate
+    nothing here either.  Calls whose work overlaps on one GPU race on the
+    shared counters: keep them on one stream."""
+
+    def solve(self, time_domain, state, params, *, next_h=None, system_index=None, out=None,
+              stream=None, **options: Any) -> dict:
+        """As :meth:`Ensemble.solve`."""
+        import torch
+        a, out, _ = self._args(time_domain, state, params, next_h, system_index, out, options)
+        if stream is None:
+            stream = torch.cuda.current_stream(time_domain.device)
+        _check(load_library().ode_ensemble_solve_noalloc(C.byref(self._desc), C.byref(a),
+                                                         C.c_void_p(stream.cuda_stream)))
         return out
 
 

@@ -77,6 +77,9 @@ def test_create_rejects_bad_descriptors_before_any_gpu_call(lib, desc):
     assert rc in (E.EINVAL, E.ENOTSUP)
     assert h.value is None
     assert lib.ode_ensemble_last_error().decode()
+    # the allocation-free solve checks the same descriptor before any HIP call
+    a = E.SolveArgs()
+    assert lib.ode_ensemble_solve_noalloc(C.byref(d), C.byref(a), None) in (E.EINVAL, E.ENOTSUP)
 
 
 def test_null_arguments(lib):
@@ -84,6 +87,11 @@ def test_null_arguments(lib):
     assert lib.ode_ensemble_create(None, None) == E.EINVAL
     a = E.SolveArgs()
     assert lib.ode_ensemble_solve(None, C.byref(a), None) == E.EINVAL
+    assert lib.ode_ensemble_solve_noalloc(None, C.byref(a), None) == E.EINVAL
+    assert lib.ode_ensemble_solve_noalloc(C.byref(E.Desc(1, 0, 0, 0)), None, None) == E.EINVAL
+    bad = E.SolveArgs()
+    bad.n_systems, bad.ld = 5, 1  # ld < n_systems
+    assert lib.ode_ensemble_solve_noalloc(C.byref(E.Desc(1, 0, 0, 0)), C.byref(bad), None) == E.EINVAL
     assert lib.ode_ensemble_solve_segments(None, C.byref(a), 1, 1.0, 1, None, None) == E.EINVAL
     r = E.TuneResult()
     assert lib.ode_ensemble_tune(None, C.byref(a), 1.0, None, C.byref(r)) == E.EINVAL
