@@ -364,6 +364,88 @@ int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *args, double probe_
                       double probe_tolerance_scale, int64_t *index_out, int64_t capacity,
                       int64_t *n_positions, void *hip_stream);
 
+/* ---- Served queues: continuous admission into a running launch ----
+ *
+ * Not part of the paper, whose Solve integrates one fixed chunk of systems per
+ * launch (Sec. 6.3-6.4).  A served launch is a persistent integrator launch
+ * that keeps taking systems while the host appends them, so requests that
+ * arrive while others are integrating start on the lanes that free up,
+ * without waiting for a launch to end.
+ *
+ * The caller owns a pool of `ld` slots: the arrays of an ode_solve_args with
+ * leading dimension ld (inputs, outputs, and the per-system record_start and
+ * tolerances, which let requests with different windows and tolerances share
+ * the launch), a position ring (args->system_index, [ld] int64: queue
+ * position q holds the system in slot system_index[q % ld]) and
+ * request_of_slot ([ld] int32: the request each slot's system belongs to, in
+ * [0, max_requests)).  To admit a request of m systems into free slots:
+ *   1. copy its inputs into the slots, its request id into request_of_slot
+ *      and its slots into the next m ring entries, all on one stream
+ *      (`copy_stream`);
+ *   2. ode_serve_begin_request(request, m);
+ *   3. ode_serve_publish(published + m).
+ * A slot, its ring entry and its request id must stay unchanged from step 1
+ * until the request's done flag is set.  The flag (ode_serve_done_flags,
+ * host memory) turns 1 once every system of the request has been integrated
+ * and its results written back to the pool; the caller then copies the
+ * results out and may reuse the slots.  Positions are published in order and
+ * each is taken once.
+ *
+ * Every wait of the launch is bounded: a wave with no work polls the
+ * published count, sleeping between polls, and leaves after idle_polls
+ * empty polls in a row, or at once when the queue is closed and every
+ * published position is taken.  A launch that has left while positions are
+ * still unpublished-or-untaken is simply launched again (ode_serve_launch
+ * continues from the queue's position).  Results are bit-identical to an
+ * ode_ensemble_solve of the same systems: no system's arithmetic depends on
+ * its lane, its neighbours or the time it was admitted.
+ *
+ * Memory: the queue owns 32 bytes of device counters, max_requests int32
+ * device counts, and max_requests int32 flags in coherent host memory.  One
+ * served launch per queue may run at a time. */
+typedef struct ode_serve ode_serve;
+
+/* Create a served queue on the current device for up to max_requests
+ * request ids (1 .. 2^24).  Errors: ODE_EINVAL, ODE_ENOMEM. */
+int ode_serve_create(int32_t max_requests, ode_serve **out);
+
+/* Host pointer to the max_requests done flags (coherent host memory, written
+ * by the GPU); NULL for a NULL queue. */
+volatile int32_t *ode_serve_done_flags(ode_serve *s);
+
+/* Start a new session: published count, closed flag and queue position to
+ * zero, every done flag to 0.  No launch may be running.  Synchronous on
+ * copy_stream.  Errors: ODE_EINVAL, ODE_EHIP. */
+int ode_serve_reset(ode_serve *s, void *copy_stream);
+
+/* Arm request `request` (in [0, max_requests)) for n_systems >= 1 systems:
+ * its done flag to 0 and its device count to n_systems.  Synchronous on
+ * copy_stream (so the copies enqueued there before have completed).
+ * Errors: ODE_EINVAL, ODE_EHIP. */
+int ode_serve_begin_request(ode_serve *s, int32_t request, int32_t n_systems, void *copy_stream);
+
+/* Set the published count to `published` (positions [0, published) may be
+ * taken).  Synchronous on copy_stream: everything enqueued there before has
+ * completed when the count changes.  Errors: ODE_EINVAL, ODE_EHIP. */
+int ode_serve_publish(ode_serve *s, int64_t published, void *copy_stream);
+
+/* Close the queue: running waves leave once every published position is
+ * taken.  Synchronous on copy_stream.  Errors: ODE_EINVAL, ODE_EHIP. */
+int ode_serve_close(ode_serve *s, void *copy_stream);
+
+/* Enqueue a served launch of handle e on hip_stream over the pool described
+ * by args (system_index is the position ring; n_systems is ignored; the other
+ * fields as for ode_ensemble_solve, with ld the pool size).  At most
+ * max_workgroups workgroups (0: as many as are resident), so several served
+ * launches of different models can share the device.  idle_polls >= 1 bounds
+ * the idle wait (see above).  Errors: ODE_EINVAL, ODE_EHIP. */
+int ode_serve_launch(ode_serve *s, ode_ensemble *e, const ode_solve_args *args,
+                     const int32_t *request_of_slot, int32_t max_workgroups, int32_t idle_polls,
+                     void *hip_stream);
+
+/* Release the queue's memory (no launch may be running).  NULL is ignored. */
+void ode_serve_destroy(ode_serve *s);
+
 /* Launch facts for the handle.  Errors: ODE_EINVAL for NULL arguments. */
 int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info);
 

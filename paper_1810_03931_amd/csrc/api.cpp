@@ -473,6 +473,156 @@ extern "C" int ode_ensemble_solve_noalloc(const ode_ensemble_desc *desc, const o
   return ODE_OK;
 }
 
+// ---- Served queues (ode_serve_*) ----
+
+struct ode_serve {
+  int device;
+  int32_t max_requests;
+  // device memory: [0] published positions (int64), [1] closed (int32 in the
+  // low half), then the queue counters [2][3] and the requests' counts
+  int64_t *dev_words;
+  int32_t *req_left;     // device [max_requests]
+  int32_t *req_done;     // host, coherent and mapped [max_requests]
+  int32_t *req_done_dev; // the same memory as the device addresses it
+  int64_t *stage;        // host, pinned: staging words for the small copies
+};
+
+namespace {
+constexpr int kServeWords = 4;   // published, closed, queue position, finished waves
+constexpr int kStageCount = kServeWords + 1;   // + one staging word for a request's count
+
+int serve_copy_word(ode_serve *s, int index, int64_t value, hipStream_t st) {
+  // the host staging word stays unchanged until the copy has completed: the
+  // call waits for the stream
+  s->stage[index] = value;
+  hipError_t err = hipMemcpyAsync(s->dev_words + index, s->stage + index, sizeof(int64_t),
+                                  hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  if (err != hipSuccess) return hip_fail(err, "copying a served-queue word");
+  return ODE_OK;
+}
+}  // namespace
+
+extern "C" int ode_serve_create(int32_t max_requests, ode_serve **out) {
+  if (!out) return fail(ODE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_requests < 1 || max_requests > (1 << 24))
+    return fail(ODE_EINVAL, "max_requests must be in [1, 2^24]");
+  auto *s = static_cast<ode_serve *>(std::calloc(1, sizeof(ode_serve)));
+  if (!s) return fail(ODE_ENOMEM, "host allocation failed");
+  s->max_requests = max_requests;
+  hipError_t err = hipGetDevice(&s->device);
+  if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void **>(&s->dev_words),
+                                         kServeWords * sizeof(int64_t));
+  if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void **>(&s->req_left),
+                                         sizeof(int32_t) * max_requests);
+  if (err == hipSuccess)
+    err = hipHostMalloc(reinterpret_cast<void **>(&s->req_done), sizeof(int32_t) * max_requests,
+                        hipHostMallocCoherent | hipHostMallocMapped);
+  if (err == hipSuccess)
+    err = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->req_done_dev), s->req_done, 0);
+  if (err == hipSuccess)
+    err = hipHostMalloc(reinterpret_cast<void **>(&s->stage), kStageCount * sizeof(int64_t),
+                        hipHostMallocDefault);
+  if (err == hipSuccess) err = hipMemset(s->dev_words, 0, kServeWords * sizeof(int64_t));
+  if (err == hipSuccess) err = hipMemset(s->req_left, 0, sizeof(int32_t) * max_requests);
+  if (err == hipSuccess) err = hipDeviceSynchronize();
+  if (err != hipSuccess) {
+    ode_serve_destroy(s);
+    return fail(ODE_ENOMEM, "allocating a served queue: %s", hipGetErrorString(err));
+  }
+  std::memset(s->req_done, 0, sizeof(int32_t) * max_requests);
+  *out = s;
+  return ODE_OK;
+}
+
+extern "C" void ode_serve_destroy(ode_serve *s) {
+  if (!s) return;
+  if (s->dev_words) (void)hipFree(s->dev_words);
+  if (s->req_left) (void)hipFree(s->req_left);
+  if (s->req_done) (void)hipHostFree(s->req_done);
+  if (s->stage) (void)hipHostFree(s->stage);
+  std::free(s);
+}
+
+extern "C" volatile int32_t *ode_serve_done_flags(ode_serve *s) {
+  return s ? s->req_done : nullptr;
+}
+
+extern "C" int ode_serve_reset(ode_serve *s, void *copy_stream) {
+  if (!s) return fail(ODE_EINVAL, "NULL served queue");
+  const hipStream_t st = static_cast<hipStream_t>(copy_stream);
+  for (int w = 0; w < kServeWords; ++w) {
+    const int rc = serve_copy_word(s, w, 0, st);
+    if (rc != ODE_OK) return rc;
+  }
+  std::memset(const_cast<int32_t *>(s->req_done), 0, sizeof(int32_t) * s->max_requests);
+  return ODE_OK;
+}
+
+extern "C" int ode_serve_begin_request(ode_serve *s, int32_t request, int32_t n_systems,
+                                       void *copy_stream) {
+  if (!s) return fail(ODE_EINVAL, "NULL served queue");
+  if (request < 0 || request >= s->max_requests)
+    return fail(ODE_EINVAL, "request %d outside [0, %d)", request, s->max_requests);
+  if (n_systems < 1) return fail(ODE_EINVAL, "a request needs at least one system");
+  const hipStream_t st = static_cast<hipStream_t>(copy_stream);
+  __atomic_store_n(s->req_done + request, 0, __ATOMIC_RELEASE);
+  int32_t *n32 = reinterpret_cast<int32_t *>(s->stage + kServeWords);
+  *n32 = n_systems;
+  hipError_t err = hipMemcpyAsync(s->req_left + request, n32, sizeof(int32_t),
+                                  hipMemcpyHostToDevice, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  if (err != hipSuccess) return hip_fail(err, "setting a request's count");
+  return ODE_OK;
+}
+
+extern "C" int ode_serve_publish(ode_serve *s, int64_t published, void *copy_stream) {
+  if (!s) return fail(ODE_EINVAL, "NULL served queue");
+  if (published < 0) return fail(ODE_EINVAL, "published < 0");
+  return serve_copy_word(s, 0, published, static_cast<hipStream_t>(copy_stream));
+}
+
+extern "C" int ode_serve_close(ode_serve *s, void *copy_stream) {
+  if (!s) return fail(ODE_EINVAL, "NULL served queue");
+  return serve_copy_word(s, 1, 1, static_cast<hipStream_t>(copy_stream));
+}
+
+extern "C" int ode_serve_launch(ode_serve *s, ode_ensemble *e, const ode_solve_args *a,
+                                const int32_t *request_of_slot, int32_t max_workgroups,
+                                int32_t idle_polls, void *hip_stream) {
+  if (!s || !e || !a) return fail(ODE_EINVAL, "NULL served queue, handle or arguments");
+  if (!a->system_index) return fail(ODE_EINVAL, "a served launch needs the position ring (system_index)");
+  if (!request_of_slot) return fail(ODE_EINVAL, "request_of_slot is NULL");
+  if (max_workgroups < 0) return fail(ODE_EINVAL, "max_workgroups < 0");
+  if (idle_polls < 1) return fail(ODE_EINVAL, "idle_polls must be >= 1");
+  ode_solve_args v = *a;
+  v.n_systems = a->ld;   // the ring: every slot may be taken
+  int rc = validate(e, &v);
+  if (rc != ODE_OK) return rc;
+  if (v.ld < 1) return fail(ODE_EINVAL, "ld must be >= 1");
+  Params prm;
+  int nev = 0, nacc = 0, grid = 0;
+  rc = prepare_launch(e, &v, prm, nev, nacc, grid);
+  if (rc != ODE_OK) return rc;
+  if (max_workgroups > 0 && grid > max_workgroups) grid = max_workgroups;
+  Arrays &arr = prm.a;
+  arr.queue = reinterpret_cast<unsigned long long *>(s->dev_words + 2);
+  arr.total_waves = static_cast<uint32_t>(grid) * static_cast<uint32_t>(e->block / 64);
+  arr.avail = s->dev_words;
+  arr.closed = reinterpret_cast<const int32_t *>(s->dev_words + 1);
+  arr.req_of = request_of_slot;
+  arr.req_left = s->req_left;
+  arr.req_done = s->req_done_dev;
+  arr.n_req = s->max_requests;
+  arr.idle_polls = idle_polls;
+  e->last_grid = grid;
+  const hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid,
+                                           e->block, static_cast<hipStream_t>(hip_stream));
+  if (err != hipSuccess) return hip_fail(err, "served launch");
+  return ODE_OK;
+}
+
 // Records the whole repeated-horizon sequence on the handle's private stream.
 static int record_segments(ode_ensemble *e, const ode_solve_args *a, int32_t n_segments,
                            double segment, int32_t first_snapshot, double *snapshots,

@@ -68,6 +68,21 @@ struct Arrays {
   int64_t n, ld;
   unsigned long long *queue;  // [0] next queue position, [1] finished waves
   uint32_t total_waves;
+  // Served launches (avail != nullptr): queue position q holds the system in
+  // slot index[q % ld]; positions below *avail are published (written by the
+  // host with copies on its own stream while the launch runs).  Waves keep
+  // taking published positions until *closed is set and every published
+  // position is taken, or until they have polled idle_polls times in a row
+  // without finding work.  A system's request (req_of[slot]) is finished when
+  // req_left drops to zero; the last system of a request sets req_done[r] in
+  // host-visible memory.
+  const int64_t *avail;
+  const int32_t *closed;
+  const int32_t *req_of;
+  int32_t *req_left;
+  int32_t *req_done;
+  int32_t n_req;
+  int32_t idle_polls;
 };
 
 // Everything one launch needs, passed as the single by-value kernel argument.

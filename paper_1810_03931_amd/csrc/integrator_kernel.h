@@ -317,7 +317,23 @@ __device__ __forceinline__ Arrays arrays_of(ParamsRef q) {
   a.ld = q->a.ld;
   a.queue = q->a.queue;
   a.total_waves = q->a.total_waves;
+  a.avail = q->a.avail;
+  a.closed = q->a.closed;
+  a.req_of = q->a.req_of;
+  a.req_left = q->a.req_left;
+  a.req_done = q->a.req_done;
+  a.n_req = q->a.n_req;
+  a.idle_polls = q->a.idle_polls;
   return a;
+}
+
+// Served launches read what the host publishes while they run (copies on
+// another stream, then the published count).  These loads are system-scope
+// atomics, so they bypass any cache line that an earlier read of the same
+// address left behind: slots and queue entries are reused for later requests.
+template <class T>
+__device__ __forceinline__ T load_published(const T *p) {
+  return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ EventCtl event_of(ParamsRef q, int j) {
@@ -444,6 +460,8 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   bool first_fill = true;  // wave-uniform
   const uint32_t wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   uint32_t iter = 0;       // loop iterations of this wave (wave-uniform)
+  int32_t idle = 0;        // served launches: empty polls in a row (wave-uniform)
+  int32_t req = 0;         // served launches: request of the lane's system
 
   auto acc_init = [&]() {
 #pragma unroll
@@ -485,6 +503,15 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       for (int j = 0; j < NEV; ++j)
         if (j < c.n_events) a.evc[j * ld + s] = wcnt[j];
     }
+    if (a.avail) {
+      // served: the results are written back before the request's count
+      // drops, and the request's last system raises its flag in host memory
+      __threadfence_system();
+      if (req >= 0 && req < a.n_req && atomicSub(a.req_left + req, 1) == 1) {
+        __threadfence_system();
+        __hip_atomic_store(a.req_done + req, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
     active = false;
   };
 
@@ -499,8 +526,63 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       const Arrays a = arrays_of(q);
       const int64_t ld = a.ld;
       const uint32_t k = __popcll(need);
-      unsigned long long base = 0;
-      if (first_fill && (unsigned long long)a.total_waves * 64ull >= (unsigned long long)a.n) {
+      const bool served = a.avail != nullptr;
+      unsigned long long base = 0, lim = (unsigned long long)a.n;  // positions [base, lim)
+      if (served) {
+        // Take up to k published positions: lane 0 advances the queue
+        // counter with compare-and-swap, never beyond the published count.
+        // While some lanes still integrate, poll every 16 iterations only.
+        const bool all_idle = need == ~0ull;
+        lim = 0;
+        if (all_idle || (iter & 15u) == 0u) {
+          unsigned long long b = 0, e = 0;
+          if (lane == 0) {
+            const unsigned long long av =
+                (unsigned long long)__hip_atomic_load(const_cast<int64_t *>(a.avail), __ATOMIC_ACQUIRE,
+                                                      __HIP_MEMORY_SCOPE_SYSTEM);
+            unsigned long long old =
+                __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int tries = 0; tries < 64; ++tries) {
+              const unsigned long long want = (old + k < av) ? old + k : av;
+              if (want <= old) break;
+              if (__hip_atomic_compare_exchange_strong(a.queue, &old, want, __ATOMIC_RELAXED,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                b = old;
+                e = want;
+                break;
+              }
+            }
+          }
+          base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+                 (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)b);
+          lim = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32)) << 32) |
+                (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)e);
+          if (lim > base) {
+            idle = 0;
+          } else if (all_idle) {
+            // Nothing to take.  Leave once the host has closed the queue and
+            // every published position is taken, or after idle_polls empty
+            // polls in a row (a bounded wait: the host relaunches if work
+            // arrives later).
+            int stop = 0;
+            if (lane == 0) {
+              const int32_t cl = __hip_atomic_load(const_cast<int32_t *>(a.closed), __ATOMIC_ACQUIRE,
+                                                   __HIP_MEMORY_SCOPE_SYSTEM);
+              const unsigned long long av = (unsigned long long)__hip_atomic_load(
+                  const_cast<int64_t *>(a.avail), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+              const unsigned long long qv =
+                  __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              stop = (cl != 0 && qv >= av) ? 1 : 0;
+            }
+            stop = __builtin_amdgcn_readfirstlane(stop);
+            if (stop != 0 || ++idle >= a.idle_polls) {
+              exhausted = true;
+            } else {
+              __builtin_amdgcn_s_sleep(127);
+            }
+          }
+        }
+      } else if (first_fill && (unsigned long long)a.total_waves * 64ull >= (unsigned long long)a.n) {
         // Every system has a lane from the start: wave w takes queue
         // positions 64w .. 64w + 63, so the queue order decides which systems
         // share a SIMD.  The waves of the first 256 workgroups (one per CU)
@@ -523,19 +605,31 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
             (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
         const unsigned long long pos = base + rank;
-        if (pos < (unsigned long long)a.n) {
-          const int64_t cand = a.index ? a.index[pos] : (int64_t)pos;
+        if (pos < lim) {
+          const int64_t cand = served ? load_published(a.index + pos % (unsigned long long)ld)
+                                      : (a.index ? a.index[pos] : (int64_t)pos);
           if (cand >= 0 && cand < ld) {
             s = cand;
             active = true;
             // ---- load and initialise the system ----
-            t = a.td[s];
-            t1 = a.td[ld + s];
-            t_rec = a.t_rec ? a.t_rec[s] : c.t_record;
+            if (served) {
+              req = load_published(a.req_of + s);
+              t = load_published(a.td + s);
+              t1 = load_published(a.td + ld + s);
+              t_rec = a.t_rec ? load_published(a.t_rec + s) : c.t_record;
 #pragma unroll
-            for (int i = 0; i < N; ++i) y[i] = a.y[i * ld + s];
+              for (int i = 0; i < N; ++i) y[i] = load_published(a.y + i * ld + s);
 #pragma unroll
-            for (int j = 0; j < P; ++j) p[j] = a.p[j * ld + s];
+              for (int j = 0; j < P; ++j) p[j] = load_published(a.p + j * ld + s);
+            } else {
+              t = a.td[s];
+              t1 = a.td[ld + s];
+              t_rec = a.t_rec ? a.t_rec[s] : c.t_record;
+#pragma unroll
+              for (int i = 0; i < N; ++i) y[i] = a.y[i * ld + s];
+#pragma unroll
+              for (int j = 0; j < P; ++j) p[j] = a.p[j * ld + s];
+            }
             if constexpr (PREC == kPrecMixed) {
               M::prepare32(p, pf);
             }
@@ -543,7 +637,9 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             if (METHOD == kMethodRKCK45 && a.tol) {
 #pragma unroll
               for (int i = 0; i < N; ++i) {
-                const double rt = a.tol[i * ld + s], at = a.tol[(N + i) * ld + s];
+                const double rt = served ? load_published(a.tol + i * ld + s) : a.tol[i * ld + s];
+                const double at =
+                    served ? load_published(a.tol + (N + i) * ld + s) : a.tol[(N + i) * ld + s];
                 tol_ok = tol_ok && rt >= 0.0 && at >= 0.0 && rt + at > 0.0 &&
                          rt + at < __builtin_huge_val();
                 hc.rtol[i] = rt;
@@ -562,7 +658,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             } else {
               h = c.h0;
               if (a.next_h) {
-                const double hn = a.next_h[s];
+                const double hn = served ? load_published(a.next_h + s) : a.next_h[s];
                 if (hn > 0.0 && isfinite(hn)) h = hn;
               }
               h = fmin(fmax(h, c.h_min), c.h_max);
@@ -892,14 +988,17 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     if (status != kRunning) retire();
   }
 
-  // The last wave to leave resets the queue for the next launch.
+  // The last wave to leave resets the queue for the next launch.  (A served
+  // queue keeps its position: a later launch continues from it.)
   if (lane == 0) {
     const Arrays a = arrays_of(fresh_params());
-    __threadfence();
-    const unsigned long long done = atomicAdd(a.queue + 1, 1ull);
-    if (done + 1 == (unsigned long long)a.total_waves) {
-      atomicExch(a.queue, 0ull);
-      atomicExch(a.queue + 1, 0ull);
+    if (!a.avail) {
+      __threadfence();
+      const unsigned long long done = atomicAdd(a.queue + 1, 1ull);
+      if (done + 1 == (unsigned long long)a.total_waves) {
+        atomicExch(a.queue, 0ull);
+        atomicExch(a.queue + 1, 0ull);
+      }
     }
   }
 }

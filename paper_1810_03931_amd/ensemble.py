@@ -85,7 +85,9 @@ class Info(C.Structure):
 
 EXPORTS = ("ode_ensemble_model_dims", "ode_ensemble_create", "ode_ensemble_solve",
            "ode_ensemble_solve_noalloc", "ode_ensemble_solve_segments", "ode_ensemble_tune",
-           "ode_ensemble_plan", "ode_plan_order", "ode_ensemble_query", "ode_ensemble_destroy",
+           "ode_ensemble_plan", "ode_plan_order", "ode_serve_create", "ode_serve_done_flags",
+           "ode_serve_reset", "ode_serve_begin_request", "ode_serve_publish", "ode_serve_close",
+           "ode_serve_launch", "ode_serve_destroy", "ode_ensemble_query", "ode_ensemble_destroy",
            "ode_ensemble_last_error")
 
 _lib = None
@@ -139,6 +141,22 @@ def load_library(path: str = LIB_PATH):
     L.ode_plan_order.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                                  C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]
     L.ode_plan_order.restype = C.c_int
+    L.ode_serve_create.argtypes = [C.c_int32, C.POINTER(C.c_void_p)]
+    L.ode_serve_create.restype = C.c_int
+    L.ode_serve_done_flags.argtypes = [C.c_void_p]
+    L.ode_serve_done_flags.restype = C.c_void_p
+    for f in ("ode_serve_reset", "ode_serve_close"):
+        getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
+        getattr(L, f).restype = C.c_int
+    L.ode_serve_begin_request.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+    L.ode_serve_begin_request.restype = C.c_int
+    L.ode_serve_publish.argtypes = [C.c_void_p, C.c_int64, C.c_void_p]
+    L.ode_serve_publish.restype = C.c_int
+    L.ode_serve_launch.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(SolveArgs), C.c_void_p,
+                                   C.c_int32, C.c_int32, C.c_void_p]
+    L.ode_serve_launch.restype = C.c_int
+    L.ode_serve_destroy.argtypes = [C.c_void_p]
+    L.ode_serve_destroy.restype = None
     L.ode_ensemble_query.argtypes = [C.c_void_p, C.POINTER(Info)]
     L.ode_ensemble_query.restype = C.c_int
     L.ode_ensemble_destroy.argtypes = [C.c_void_p]
@@ -417,6 +435,102 @@ class NoAllocSolver(_Solver):
         _check(load_library().ode_ensemble_solve_noalloc(C.byref(self._desc), C.byref(a),
                                                          C.c_void_p(stream.cuda_stream)))
         return out
+
+
+class ServedQueue:
+    """A served queue (``ode_serve_*``): continuous admission of systems into
+    a running persistent launch.  The caller owns the slot pool; this object
+    owns the queue's counters and the requests' done flags."""
+
+    def __init__(self, max_requests: int):
+        import numpy as np
+        L = load_library()
+        h = C.c_void_p()
+        _check(L.ode_serve_create(int(max_requests), C.byref(h)))
+        self._h = h
+        self.max_requests = int(max_requests)
+        flags = L.ode_serve_done_flags(h)
+        self.done = np.ctypeslib.as_array(C.cast(flags, C.POINTER(C.c_int32)),
+                                          shape=(self.max_requests,))
+
+    def close_queue(self, stream):
+        _check(load_library().ode_serve_close(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def reset(self, stream):
+        _check(load_library().ode_serve_reset(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def begin_request(self, request: int, n_systems: int, stream):
+        _check(load_library().ode_serve_begin_request(self._h, int(request), int(n_systems),
+                                                      C.c_void_p(stream.cuda_stream)))
+
+    def publish(self, published: int, stream):
+        _check(load_library().ode_serve_publish(self._h, int(published),
+                                                C.c_void_p(stream.cuda_stream)))
+
+    def launch(self, ens: "Ensemble", time_domain, state, params, ring, request_of_slot, *,
+               out, next_h=None, max_workgroups: int = 0, idle_polls: int = 2000, stream=None,
+               **options: Any):
+        """Enqueue a served launch of ``ens`` over the slot pool (``ring``:
+        int64 position ring [ld]; ``request_of_slot``: int32 [ld])."""
+        import torch
+        ld = int(time_domain.shape[-1])
+        if ring is None or ring.numel() < ld:
+            raise ValueError("ring: need an int64 CUDA tensor of one entry per slot")
+        a, out, _ = ens._args(time_domain, state, params, next_h, ring, out, options)
+        rq = _ptr(request_of_slot, torch.int32, 1, ld, "request_of_slot")
+        if stream is None:
+            stream = torch.cuda.current_stream(time_domain.device)
+        _check(load_library().ode_serve_launch(self._h, ens._h, C.byref(a), C.c_void_p(rq),
+                                               int(max_workgroups), int(idle_polls),
+                                               C.c_void_p(stream.cuda_stream)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            load_library().ode_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy2DAsync.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+                                          C.c_size_t, C.c_size_t, C.c_int, C.c_void_p]
+        _hip.hipMemcpy2DAsync.restype = C.c_int
+    return _hip
+
+
+def copy_columns(dst, dst_col: int, src, src_col: int, ncols: int, stream) -> None:
+    """Columns [src_col, src_col + ncols) of every row of ``src`` into columns
+    [dst_col, dst_col + ncols) of ``dst``, as one strided copy
+    (hipMemcpy2DAsync) on ``stream``.  Both are C-contiguous tensors of one
+    dtype and the same number of rows (the last axis is the column axis, the
+    others are rows); host tensors must be pinned.  Asynchronous."""
+    if dst.dtype != src.dtype or not dst.is_contiguous() or not src.is_contiguous():
+        raise ValueError("copy_columns: need contiguous tensors of one dtype")
+    rows_d, rows_s = dst.numel() // dst.shape[-1], src.numel() // src.shape[-1]
+    if rows_d != rows_s:
+        raise ValueError(f"copy_columns: {rows_d} rows into {rows_s}")
+    if ncols <= 0:
+        return
+    if dst_col < 0 or src_col < 0 or dst_col + ncols > dst.shape[-1] or src_col + ncols > src.shape[-1]:
+        raise ValueError("copy_columns: columns out of range")
+    es = dst.element_size()
+    rc = _hip_runtime().hipMemcpy2DAsync(
+        dst.data_ptr() + dst_col * es, dst.shape[-1] * es, src.data_ptr() + src_col * es,
+        src.shape[-1] * es, ncols * es, rows_d, 4, C.c_void_p(stream.cuda_stream))  # 4: by address
+    if rc != 0:
+        raise OdeError(EHIP, f"hipMemcpy2DAsync failed ({rc})")
 
 
 def solve_problem(pb, *, device="cuda", block_size: int = 0, stream=None, ens=None):

@@ -226,6 +226,240 @@ class Server:
         return [results[r.rid] for r in requests]
 
 
+class _Resident:
+    """The served launch of one kernel class (model, method, events and
+    accessories): a pool of ``capacity`` slots on the device, its position
+    ring and a served queue.  Requests are copied into free slots and
+    published while the launch runs, and their systems start on the lanes
+    that free up; a request's slots are released once its results are back.
+    Event records are not part of a served result, so the pool keeps none."""
+
+    def __init__(self, torch, device, first: I.Problem, *, capacity: int, precision: str,
+                 block_size: int, max_workgroups: int, idle_polls: int, max_requests: int):
+        self.torch = torch
+        self.model, self.method = first.model, first.method
+        opts = {k: v for k, v in first.options.items() if k not in PER_SYSTEM}
+        opts["events"] = [dict(e, record_component=-1) for e in opts.get("events", [])]
+        opts["record_cap"] = 0
+        self.options = opts
+        ns, npar = first.state.shape[0], first.params.shape[0]
+        self.cap = C = int(capacity)
+        f64 = torch.float64
+        self.td = torch.zeros((2, C), dtype=f64, device=device)
+        self.y = torch.zeros((ns, C), dtype=f64, device=device)
+        self.p = torch.zeros((npar, C), dtype=f64, device=device)
+        self.rec = torch.zeros(C, dtype=f64, device=device)
+        self.tol = torch.ones((2 * ns, C), dtype=f64, device=device)
+        self.ring = torch.zeros(C, dtype=torch.int64, device=device)
+        self.req_of = torch.zeros(C, dtype=torch.int32, device=device)
+        self.ens = E.Ensemble(self.model, self.method, precision=precision, block_size=block_size)
+        self.out = self.ens.outputs(C, n_accessories=len(opts.get("accessories", [])),
+                                    n_events=len(opts["events"]), device=device)
+        self.queue = E.ServedQueue(max_requests)
+        self.stream = torch.cuda.Stream(device=device)
+        self.copy = torch.cuda.Stream(device=device)
+        self.max_requests = int(max_requests)
+        self.max_workgroups = int(max_workgroups)
+        self.idle_polls = int(idle_polls)
+        self.launches = 0
+        self.reset()
+
+    def reset(self):
+        """A new session (no launch may be running)."""
+        self.queue.reset(self.copy)
+        self.free = [(0, self.cap)]        # free slot ranges (start, length), sorted
+        self.ids = list(range(self.max_requests - 1, -1, -1))
+        self.published = 0
+        self.launched = None               # completion event of the latest launch
+        self.inflight = {}                 # request id -> (request, arrival, admitted, start)
+
+    def _alloc(self, m: int):
+        for i, (a, length) in enumerate(self.free):
+            if length >= m:
+                self.free[i:i + 1] = [] if length == m else [(a + m, length - m)]
+                return a
+        return None
+
+    def _release(self, a: int, m: int):
+        merged = []
+        for s, length in sorted(self.free + [(a, m)]):
+            if merged and merged[-1][0] + merged[-1][1] == s:
+                merged[-1] = (merged[-1][0], merged[-1][1] + length)
+            else:
+                merged.append((s, length))
+        self.free = merged
+
+    def admit(self, req, arrival: float, now: float) -> bool:
+        """Copy a request into free slots and publish its systems; False when
+        no slot range or request id is free."""
+        pb = req.problem
+        m = pb.n
+        if not self.ids or m > self.cap:
+            return False
+        a = self._alloc(m)
+        if a is None:
+            return False
+        rid = self.ids.pop()
+        torch = self.torch
+        pin = lambda x: torch.from_numpy(np.ascontiguousarray(x)).pin_memory()
+        host = [(self.td, pin(pb.time_domain)), (self.y, pin(pb.state)), (self.p, pin(pb.params)),
+                (self.rec, pin(np.full(m, pb.options.get("t_record", -np.inf)))),
+                (self.req_of, pin(np.full(m, rid, dtype=np.int32)))]
+        if self.method == "rkck45":
+            host.append((self.tol, pin(_tolerances(pb))))
+        for dst, src in host:
+            E.copy_columns(dst, a, src, 0, m, self.copy)
+        # ring entries of queue positions P .. P+m-1 (wrapping at the pool size)
+        P, C = self.published, self.cap
+        slots = pin(a + np.arange(m, dtype=np.int64))
+        first = min(m, C - P % C)
+        E.copy_columns(self.ring, P % C, slots, 0, first, self.copy)
+        if first < m:
+            E.copy_columns(self.ring, 0, slots, first, m - first, self.copy)
+        self.queue.begin_request(rid, m, self.copy)    # waits for the copies above
+        self.published += m
+        self.queue.publish(self.published, self.copy)
+        self.inflight[rid] = (req, arrival, now, a)
+        self.ensure_running()
+        return True
+
+    def ensure_running(self):
+        """Launch again when requests are in flight and the latest launch has
+        left (its waves leave after idle_polls empty polls)."""
+        if not self.inflight or (self.launched is not None and not self.launched.query()):
+            return
+        opts = dict(self.options, record_start=self.rec)
+        if self.method == "rkck45":
+            opts["tolerances"] = self.tol
+        self.queue.launch(self.ens, self.td, self.y, self.p, self.ring, self.req_of, out=self.out,
+                          max_workgroups=self.max_workgroups, idle_polls=self.idle_polls,
+                          stream=self.stream, **opts)
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        self.launched = ev
+        self.launches += 1
+
+    def collect(self, t0: float) -> list:
+        """Results of the requests whose done flag is set; their slots and
+        request ids are released."""
+        torch = self.torch
+        results = []
+        for rid in [r for r in self.inflight if self.queue.done[r] == 1]:
+            req, arrival, admitted, a = self.inflight.pop(rid)
+            m = req.problem.n
+            dev = {"t": self.td[0], "y": self.y, "status": self.out["status"],
+                   "counts": self.out["counts"]}
+            for k in ("acc", "event_counts"):
+                if self.out.get(k) is not None:
+                    dev[k] = self.out[k]
+            host = {}
+            for k, v in dev.items():
+                h = torch.empty(tuple(v.shape[:-1]) + (m,), dtype=v.dtype, pin_memory=True)
+                E.copy_columns(h, 0, v, a, m, self.copy)
+                host[k] = h
+            self.copy.synchronize()
+            done = time.perf_counter() - t0
+            part = {k: v.numpy().copy() for k, v in host.items()}
+            self._release(a, m)
+            self.ids.append(rid)
+            results.append(Result(req.rid, arrival, admitted, done, int(part["counts"][0].sum()),
+                                  part))
+        self.ensure_running()
+        return results
+
+    def close(self):
+        """Close the queue and wait for the launch to leave."""
+        self.queue.close_queue(self.copy)
+        self.stream.synchronize()
+
+
+class ResidentServer:
+    """Continuous batching inside running launches: one served launch per
+    kernel class (model, method, events, accessories), each on at most
+    ``max_workgroups`` workgroups so the classes share the device, each with a
+    pool of ``capacity`` slots (the device-memory budget of its class).  A
+    request is admitted as soon as its class has a free slot range: its
+    systems are copied in and published, and the running launch's lanes take
+    them as they free up.  Arrival order is kept within a class; a request
+    that does not fit does not hold back the other classes."""
+
+    def __init__(self, *, precision: str = "fp64", capacity: int = 1 << 17,
+                 max_workgroups: int = 128, idle_polls: int = 2000, block_size: int = 0,
+                 device: int = 0, max_requests: int = 4096):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.kw = dict(capacity=capacity, precision=precision, block_size=block_size,
+                       max_workgroups=max_workgroups, idle_polls=idle_polls,
+                       max_requests=max_requests)
+        self.classes = {}
+
+    def _class(self, pb: I.Problem) -> _Resident:
+        key = _batch_key(pb)
+        if key not in self.classes:
+            self.classes[key] = _Resident(self.torch, self.device, pb, **self.kw)
+        return self.classes[key]
+
+    def run(self, requests: list, arrivals: Optional[np.ndarray] = None,
+            poll_s: float = 5e-5, stall_s: float = 600.0) -> list:
+        """Serve ``requests`` arriving at ``arrivals`` (seconds from the start;
+        None: all at once); one Result per request, in request order.  Raises
+        if no request completes for ``stall_s`` seconds while some are in
+        flight."""
+        if arrivals is None:
+            arrivals = np.zeros(len(requests))
+        for r in requests:
+            if r.problem.n > self.kw["capacity"]:
+                raise ValueError(f"request {r.rid} has more systems than a pool holds")
+        order = np.argsort(arrivals, kind="stable")
+        future = deque((requests[i], float(arrivals[i])) for i in order)
+        waiting = deque()
+        for c in self.classes.values():
+            c.reset()
+        results = {}
+        t0 = time.perf_counter()
+        progress = t0
+        while future or waiting or any(c.inflight for c in self.classes.values()):
+            now = time.perf_counter() - t0
+            while future and future[0][1] <= now:
+                waiting.append(future.popleft())
+            for c in list(self.classes.values()):
+                for r in c.collect(t0):
+                    results[r.rid] = r
+                    progress = time.perf_counter()
+            if any(c.inflight for c in self.classes.values()) and \
+                    time.perf_counter() - progress > stall_s:
+                for c in self.classes.values():
+                    c.close()
+                raise RuntimeError(f"served queues: no request finished in {stall_s} s")
+            blocked = set()
+            keep = deque()
+            while waiting:
+                req, arr = waiting.popleft()
+                c = self._class(req.problem)
+                if id(c) in blocked or not c.admit(req, arr, time.perf_counter() - t0):
+                    blocked.add(id(c))
+                    keep.append((req, arr))
+            waiting = keep
+            if not waiting and future and not any(c.inflight for c in self.classes.values()):
+                time.sleep(max(0.0, min(future[0][1] - now, 1e-3)))
+            else:
+                time.sleep(poll_s)
+        for c in self.classes.values():
+            c.close()
+        return [results[r.rid] for r in requests]
+
+    def stats(self) -> dict:
+        return {"classes": len(self.classes),
+                "launches": sum(c.launches for c in self.classes.values())}
+
+    def shutdown(self):
+        for c in self.classes.values():
+            c.close()
+            c.queue.destroy()
+        self.classes = {}
+
+
 def summarize(results: list, label: str) -> dict:
     lat = np.array([r.latency for r in results])
     span = max(r.done for r in results) - min(r.arrival for r in results)

@@ -90,3 +90,30 @@ def test_memory_budget_limits_admission(ode):
         assert inflight <= budget
     with pytest.raises(ValueError):
         Server(precision="fp64", memory_budget=budget // 4).run(reqs)
+
+
+def test_resident_results_same_alone_and_in_mix(ode):
+    """Requests admitted into running served launches (one per kernel class,
+    each on a share of the device) give bit-identical results to the same
+    request solved alone, under Poisson arrivals and when all arrive at once;
+    with a pool smaller than the mix, admission waits for slots."""
+    from paper_1810_03931_amd.serve import ResidentServer, Server
+    for prec in ("fp64", "mixed"):
+        reqs = _small_mix()
+        alone = Server(precision=prec, slots=1, max_batch_systems=0)
+        ref = [alone.run([r])[0] for r in reqs]
+        srv = ResidentServer(precision=prec, capacity=4096, max_workgroups=64)
+        arr = I.poisson_arrivals(len(reqs), 400.0, seed=1)
+        mixed = srv.run(reqs, arr, stall_s=60)
+        burst = srv.run(reqs, stall_s=60)            # all at once: slots run out
+        for a, b, c in zip(ref, mixed, burst):
+            for k in a.outputs:
+                assert np.array_equal(a.outputs[k], b.outputs[k], equal_nan=True), (prec, a.rid, k)
+                assert np.array_equal(a.outputs[k], c.outputs[k], equal_nan=True), (prec, a.rid, k)
+        st = srv.stats()
+        assert st["launches"] >= 3
+        lat = np.array([r.latency for r in mixed])
+        print(f"[serve] resident {prec}: {len(reqs)} requests identical alone, under Poisson "
+              f"arrivals and in a burst; {st}; latency p50 {np.median(lat) * 1e3:.1f} ms",
+              flush=True)
+        srv.shutdown()
