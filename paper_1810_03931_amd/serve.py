@@ -383,7 +383,7 @@ class ResidentServer:
     them as they free up.  Arrival order is kept within a class; a request
     that does not fit does not hold back the other classes."""
 
-    def __init__(self, *, precision: str = "fp64", capacity: int = 1 << 17,
+    def __init__(self, *, precision: str = "fp64", capacity: int = 1 << 21,
                  max_workgroups: int = 128, idle_polls: int = 2000, block_size: int = 0,
                  device: int = 0, max_requests: int = 4096):
         import torch
@@ -401,11 +401,12 @@ class ResidentServer:
         return self.classes[key]
 
     def run(self, requests: list, arrivals: Optional[np.ndarray] = None,
-            poll_s: float = 5e-5, stall_s: float = 600.0) -> list:
+            poll_s: float = 5e-5, stall_s: float = 600.0, progress=None) -> list:
         """Serve ``requests`` arriving at ``arrivals`` (seconds from the start;
         None: all at once); one Result per request, in request order.  Raises
         if no request completes for ``stall_s`` seconds while some are in
-        flight."""
+        flight.  ``progress(done, total, admitted)`` is called after every
+        admission and every completed request."""
         if arrivals is None:
             arrivals = np.zeros(len(requests))
         for r in requests:
@@ -418,7 +419,8 @@ class ResidentServer:
             c.reset()
         results = {}
         t0 = time.perf_counter()
-        progress = t0
+        last = t0
+        admitted = 0
         while future or waiting or any(c.inflight for c in self.classes.values()):
             now = time.perf_counter() - t0
             while future and future[0][1] <= now:
@@ -426,9 +428,11 @@ class ResidentServer:
             for c in list(self.classes.values()):
                 for r in c.collect(t0):
                     results[r.rid] = r
-                    progress = time.perf_counter()
+                    last = time.perf_counter()
+                    if progress:
+                        progress(len(results), len(requests), admitted)
             if any(c.inflight for c in self.classes.values()) and \
-                    time.perf_counter() - progress > stall_s:
+                    time.perf_counter() - last > stall_s:
                 for c in self.classes.values():
                     c.close()
                 raise RuntimeError(f"served queues: no request finished in {stall_s} s")
@@ -440,6 +444,10 @@ class ResidentServer:
                 if id(c) in blocked or not c.admit(req, arr, time.perf_counter() - t0):
                     blocked.add(id(c))
                     keep.append((req, arr))
+                else:
+                    admitted += 1
+                    if progress:
+                        progress(len(results), len(requests), admitted)
             waiting = keep
             if not waiting and future and not any(c.inflight for c in self.classes.values()):
                 time.sleep(max(0.0, min(future[0][1] - now, 1e-3)))
@@ -470,12 +478,61 @@ def summarize(results: list, label: str) -> dict:
             "system_steps_per_s": steps / span, "span_s": span, "accepted_steps": steps}
 
 
+def make_server(mode: str, precision: str, *, slots: int = 4, capacity: int = 1 << 21,
+                max_workgroups: int = 128):
+    """A server of either kind: "resident" (requests admitted into running
+    served launches, one per kernel class) or "launch" (one launch per batch
+    of requests on ``slots`` streams)."""
+    if mode == "resident":
+        return ResidentServer(precision=precision, capacity=capacity,
+                              max_workgroups=max_workgroups)
+    return Server(precision=precision, slots=slots)
+
+
+def serve_mix(reqs: list, mode: str, precisions, loads, *, slots: int = 4,
+              capacity: int = 1 << 21, max_workgroups: int = 128, log=None,
+              progress=None) -> list:
+    """Saturation (every request at t = 0) and Poisson loads at fractions of
+    the measured saturation rate, per precision; one summary per run.
+    ``progress(done, total, admitted)`` reports admissions and completions
+    (resident mode)."""
+    lines = []
+    kw = {"progress": progress} if (progress and mode == "resident") else {}
+    for prec in precisions:
+        srv = make_server(mode, prec, slots=slots, capacity=capacity,
+                          max_workgroups=max_workgroups)
+        srv.run(reqs[: min(8, len(reqs))])                     # warm up handles and kernels
+        sat = summarize(srv.run(reqs, **kw), f"{prec}/saturation")   # all requests at once
+        sat_qps = len(reqs) / sat["span_s"]
+        sat["qps"] = sat_qps
+        lines.append(sat)
+        if log:
+            log(sat)
+        for load in loads:
+            arr = I.poisson_arrivals(len(reqs), load * sat_qps)
+            st = summarize(srv.run(reqs, arr, **kw), f"{prec}/load{load}")
+            st["qps"] = load * sat_qps
+            lines.append(st)
+            if log:
+                log(st)
+        if mode == "resident":
+            srv.shutdown()
+    return lines
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="served mix: Poisson arrivals of sweep requests")
     ap.add_argument("--requests", type=int, default=600)
     ap.add_argument("--tol", type=float, nargs=2, default=[1e-7, 1e-6], metavar=("LO", "HI"),
                     help="per-request tolerance, log-uniform over [LO, HI]")
+    ap.add_argument("--mode", choices=["resident", "launch"], default="resident",
+                    help="resident: requests join running served launches; launch: one launch "
+                         "per batch on --slots streams")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--capacity", type=int, default=1 << 21,
+                    help="resident mode: slots of each kernel class's pool")
+    ap.add_argument("--max-workgroups", type=int, default=128,
+                    help="resident mode: workgroups of each class's served launch")
     ap.add_argument("--load", type=float, nargs="+", default=[0.5, 0.8],
                     help="offered load as fractions of the measured saturation rate")
     ap.add_argument("--precision", nargs="+", default=["fp64", "mixed"])
@@ -485,23 +542,21 @@ def main(argv=None) -> int:
     reqs = I.served_mix(args.requests, tol=tuple(args.tol), periods=tuple(args.periods))
     print(json.dumps({"served_mix": {"requests": len(reqs), "tolerance": args.tol,
                                      "periods": args.periods, "sizes": [256, 65536],
-                                     "models": list(I.SERVED_MODELS), "slots": args.slots}}),
-          flush=True)
-    lines = []
-    for prec in args.precision:
-        srv = Server(precision=prec, slots=args.slots)
-        srv.run(reqs[: min(8, len(reqs))])                     # warm up handles and kernels
-        sat = summarize(srv.run(reqs), f"{prec}/saturation")   # all requests at once
-        sat_qps = len(reqs) / sat["span_s"]
-        sat["qps"] = sat_qps
-        lines.append(sat)
-        print(json.dumps(sat), flush=True)
-        for load in args.load:
-            arr = I.poisson_arrivals(len(reqs), load * sat_qps)
-            st = summarize(srv.run(reqs, arr), f"{prec}/load{load}")
-            st["qps"] = load * sat_qps
-            lines.append(st)
-            print(json.dumps(st), flush=True)
+                                     "models": list(I.SERVED_MODELS), "mode": args.mode,
+                                     "slots": args.slots, "capacity": args.capacity,
+                                     "max_workgroups": args.max_workgroups}}), flush=True)
+    state = {"last": (-1, -1)}
+
+    def progress(done, total, admitted):
+        step = (done // 10, admitted // 10)
+        if step != state["last"] or done == total:
+            state["last"] = step
+            print(f"[serve] {admitted}/{total} admitted, {done}/{total} done", file=sys.stderr,
+                  flush=True)
+
+    serve_mix(reqs, args.mode, args.precision, args.load, slots=args.slots,
+              capacity=args.capacity, max_workgroups=args.max_workgroups,
+              log=lambda st: print(json.dumps(st), flush=True), progress=progress)
     return 0
 
 
