@@ -85,6 +85,29 @@ __device__ __forceinline__ double stage_time(double t, double c, double h) {
   return __dadd_rn(t, __dmul_rn(c, h));
 }
 
+// The stage weights of the FP64 attempt, read from a table in constant memory
+// through an opaque scalar pointer at the start of the attempt.  As literals,
+// each would be rebuilt by two scalar moves at every use; the loads are issued
+// with the attempt's first instructions and the first weight is needed only
+// after the first right-hand side, so their latency is hidden (27-50 fewer
+// issued instructions per attempt of a lone wave, measured on the Duffing,
+// relief-valve and Keller-Miksis kernels).  The stage-time fractions stay
+// literals: the time-only terms that start every attempt need them at once.
+enum CkWeight : int {
+  kA21, kA31, kA32, kA41, kA42, kA43, kA51, kA52, kA53, kA54, kA61, kA62, kA63, kA64, kA65,
+  kB1, kB3, kB4, kB6, kE1, kE3, kE4, kE5, kE6, kCkWeights
+};
+static __device__ __constant__ double kCkTable[kCkWeights] = {
+    ck::a21, ck::a31, ck::a32, ck::a41, ck::a42, ck::a43, ck::a51, ck::a52,
+    ck::a53, ck::a54, ck::a61, ck::a62, ck::a63, ck::a64, ck::a65, ck::b1,
+    ck::b3,  ck::b4,  ck::b6,  ck::e1,  ck::e3,  ck::e4,  ck::e5,  ck::e6};
+typedef const __attribute__((address_space(4))) double *CkTableRef;
+__device__ __forceinline__ CkTableRef ck_table() {
+  CkTableRef t = (CkTableRef)kCkTable;
+  asm volatile("" : "+s"(t));   // opaque: the weights are loaded, not folded
+  return t;
+}
+
 // One Cash-Karp step of length h from (t, y): propagated fifth-order
 // solution y5 and error estimate err = h * sum e_i k_i.  The time-only terms
 // of all six stages are evaluated first.
@@ -94,6 +117,7 @@ __device__ __forceinline__ void cash_karp_attempt(double t, const double (&y)[M:
                                                   double (&y5)[M::NS], double (&err)[M::NS]) {
   constexpr int N = M::NS;
   constexpr int FW = M::NF > 0 ? M::NF : 1;
+  const CkTableRef K = ck_table();
   const double ts[6] = {t, stage_time(t, ck::c2, h), stage_time(t, ck::c3, h),
                         stage_time(t, ck::c4, h), t + h, stage_time(t, ck::c6, h)};
   double F[6][FW];
@@ -101,32 +125,32 @@ __device__ __forceinline__ void cash_karp_attempt(double t, const double (&y)[M:
   double k1[N], k2[N], k3[N], k4[N], k5[N], k6[N], ys[N];
   M::rhs(y, p, F[0], k1);
 #pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = fma(h, ck::a21 * k1[i], y[i]);
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, K[kA21] * k1[i], y[i]);
   M::rhs(ys, p, F[1], k2);
 #pragma unroll
-  for (int i = 0; i < N; ++i) ys[i] = fma(h, fma(ck::a32, k2[i], ck::a31 * k1[i]), y[i]);
+  for (int i = 0; i < N; ++i) ys[i] = fma(h, fma(K[kA32], k2[i], K[kA31] * k1[i]), y[i]);
   M::rhs(ys, p, F[2], k3);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    ys[i] = fma(h, fma(ck::a43, k3[i], fma(ck::a42, k2[i], ck::a41 * k1[i])), y[i]);
+    ys[i] = fma(h, fma(K[kA43], k3[i], fma(K[kA42], k2[i], K[kA41] * k1[i])), y[i]);
   M::rhs(ys, p, F[3], k4);
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    ys[i] = fma(h, fma(ck::a54, k4[i], fma(ck::a53, k3[i], fma(ck::a52, k2[i], ck::a51 * k1[i]))),
+    ys[i] = fma(h, fma(K[kA54], k4[i], fma(K[kA53], k3[i], fma(K[kA52], k2[i], K[kA51] * k1[i]))),
                 y[i]);
   M::rhs(ys, p, F[4], k5);
 #pragma unroll
   for (int i = 0; i < N; ++i)
     ys[i] = fma(h,
-                fma(ck::a65, k5[i],
-                    fma(ck::a64, k4[i], fma(ck::a63, k3[i], fma(ck::a62, k2[i], ck::a61 * k1[i])))),
+                fma(K[kA65], k5[i],
+                    fma(K[kA64], k4[i], fma(K[kA63], k3[i], fma(K[kA62], k2[i], K[kA61] * k1[i])))),
                 y[i]);
   M::rhs(ys, p, F[5], k6);
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    y5[i] = fma(h, fma(ck::b6, k6[i], fma(ck::b4, k4[i], fma(ck::b3, k3[i], ck::b1 * k1[i]))), y[i]);
-    err[i] = h * fma(ck::e6, k6[i],
-                     fma(ck::e5, k5[i], fma(ck::e4, k4[i], fma(ck::e3, k3[i], ck::e1 * k1[i]))));
+    y5[i] = fma(h, fma(K[kB6], k6[i], fma(K[kB4], k4[i], fma(K[kB3], k3[i], K[kB1] * k1[i]))), y[i]);
+    err[i] = h * fma(K[kE6], k6[i],
+                     fma(K[kE5], k5[i], fma(K[kE4], k4[i], fma(K[kE3], k3[i], K[kE1] * k1[i]))));
   }
 }
 
