@@ -79,6 +79,10 @@ def parse():
     ap.add_argument("--uniform", type=int, default=-1, metavar="SYSTEM",
                     help="give every system the parameters and initial state of SYSTEM, so all "
                          "lanes step in lockstep (FLOP-per-attempt calibration with counters)")
+    ap.add_argument("--single", type=int, default=-1, metavar="SYSTEM",
+                    help="integrate only system SYSTEM of the sweep, alone (one lane of one "
+                         "wave): the time per attempt of its serial chain, which bounds a sweep "
+                         "whose end is its slowest system")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the kernel sources and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -390,6 +394,29 @@ def bench_workload(torch, E, name, args, steps, warmup):
     return rec, pb, info
 
 
+def single_system(torch, E, args):
+    """One system of the sweep integrated alone; one JSON line."""
+    pb = I.CONFIGS[args.config]().subset([args.single])
+    if args.tol > 0:
+        pb = I.with_tolerance(pb, args.tol)
+    dev = torch.device("cuda", 0)
+    td = torch.as_tensor(pb.time_domain, device=dev).contiguous()
+    y = torch.as_tensor(pb.state, device=dev).contiguous()
+    p = torch.as_tensor(pb.params, device=dev).contiguous()
+    ens = E.Ensemble(pb.model, pb.method, precision=args.precision)
+    stream = torch.cuda.current_stream(dev)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    out = ens.solve(td, y, p, stream=stream, **pb.options)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    ms = k0.elapsed_time(k1)
+    attempts = int(out["counts"].sum())
+    print(json.dumps({"workload": pb.name, "system": args.single, "precision": args.precision,
+                      "status": int(out["status"][0]), "attempts": attempts, "kernel_ms": ms,
+                      "us_per_attempt": ms * 1e3 / attempts}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -411,6 +438,9 @@ def main():
         build.build()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.single >= 0:
+        single_system(torch, E, args)
+        return
     rec, pb, info = bench_workload(torch, E, args.config, args, args.steps, args.warmup)
     line = {"metric": METRIC, "value": rec["value"], "unit": rec["unit"], "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
