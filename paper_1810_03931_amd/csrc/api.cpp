@@ -17,26 +17,27 @@
 #include "integrator.h"
 
 namespace odeens {
-const void *kernels_duffing(int method, int prec, int nev, int nacc);
-const void *kernels_keller_miksis(int method, int prec, int nev, int nacc);
-const void *kernels_relief_valve(int method, int prec, int nev, int nacc);
-const void *kernels_ballistic(int method, int prec, int nev, int nacc);
-const void *kernels_duffing_lyapunov(int method, int prec, int nev, int nacc);
+const void *kernels_duffing(int method, int prec, int nev, int nacc, int comp);
+const void *kernels_keller_miksis(int method, int prec, int nev, int nacc, int comp);
+const void *kernels_relief_valve(int method, int prec, int nev, int nacc, int comp);
+const void *kernels_ballistic(int method, int prec, int nev, int nacc, int comp);
+const void *kernels_duffing_lyapunov(int method, int prec, int nev, int nacc, int comp);
 
-const void *integrator_kernel(int model, int method, int prec, int nev, int nacc) {
+const void *integrator_kernel(int model, int method, int prec, int nev, int nacc, int comp) {
   switch (model) {
-    case ODE_MODEL_DUFFING: return kernels_duffing(method, prec, nev, nacc);
-    case ODE_MODEL_KELLER_MIKSIS: return kernels_keller_miksis(method, prec, nev, nacc);
-    case ODE_MODEL_RELIEF_VALVE: return kernels_relief_valve(method, prec, nev, nacc);
-    case ODE_MODEL_BALLISTIC: return kernels_ballistic(method, prec, nev, nacc);
-    case ODE_MODEL_DUFFING_LYAPUNOV: return kernels_duffing_lyapunov(method, prec, nev, nacc);
+    case ODE_MODEL_DUFFING: return kernels_duffing(method, prec, nev, nacc, comp);
+    case ODE_MODEL_KELLER_MIKSIS: return kernels_keller_miksis(method, prec, nev, nacc, comp);
+    case ODE_MODEL_RELIEF_VALVE: return kernels_relief_valve(method, prec, nev, nacc, comp);
+    case ODE_MODEL_BALLISTIC: return kernels_ballistic(method, prec, nev, nacc, comp);
+    case ODE_MODEL_DUFFING_LYAPUNOV:
+      return kernels_duffing_lyapunov(method, prec, nev, nacc, comp);
     default: return nullptr;
   }
 }
 
-hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc,
+hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc, int comp,
                              const Params &prm, int grid, int block, hipStream_t stream) {
-  const void *fn = integrator_kernel(model, method, prec, nev, nacc);
+  const void *fn = integrator_kernel(model, method, prec, nev, nacc, comp);
   if (!fn) return hipErrorInvalidDeviceFunction;
   Params pp = prm;
   void *args[] = {&pp};
@@ -77,12 +78,32 @@ bool model_dims(int32_t model, int32_t *ns, int32_t *np) {
 }
 
 constexpr int kDefaultBlock = 256;
-constexpr int kCombos = 9;  // (event slots 0/1/4) x (accessory slots 0/2/4)
+// (event slots 0/1/4) x (accessory slots 0/2/4) x (watched component run-time/0/1)
+constexpr int kCombos = 27;
 
-int combo_index(int nev, int nacc) {
+int combo_index(int nev, int nacc, int comp) {
   const int e = nev == 0 ? 0 : (nev == 1 ? 1 : 2);
   const int k = nacc == 0 ? 0 : (nacc == 2 ? 1 : 2);
-  return e * 3 + k;
+  return (e * 3 + k) * 3 + (comp + 1);
+}
+
+// The component every event and every extremum accessory of a solve
+// watches, when there is one and it is 0 or 1 (kernels are compiled with it
+// fixed); -1 otherwise.
+int watched_component(const ode_solve_args *a) {
+  int c = -2;
+  for (int j = 0; j < a->n_events; ++j) {
+    const int cj = a->events[j].component;
+    if (c != -2 && c != cj) return -1;
+    c = cj;
+  }
+  for (int k = 0; k < a->n_accessories; ++k) {
+    if (a->accessory_specs[k].kind == ODE_ACC_LOG_RESET) continue;
+    const int ck = a->accessory_specs[k].component;
+    if (c != -2 && c != ck) return -1;
+    c = ck;
+  }
+  return (c == 0 || c == 1) ? c : -1;
 }
 
 }  // namespace
@@ -208,10 +229,10 @@ void ode_ensemble_destroy(ode_ensemble *e) {
 
 // Resident workgroups per CU for a block size and slot combination, after
 // the handle's cap.
-static int query_blocks(ode_ensemble *e, int block, int nev, int nacc, int *out) {
-  int &slot = e->blocks_per_cu[block / 64 - 1][combo_index(nev, nacc)];
+static int query_blocks(ode_ensemble *e, int block, int nev, int nacc, int comp, int *out) {
+  int &slot = e->blocks_per_cu[block / 64 - 1][combo_index(nev, nacc, comp)];
   if (slot == 0) {
-    const void *fn = integrator_kernel(e->model, e->method, e->precision, nev, nacc);
+    const void *fn = integrator_kernel(e->model, e->method, e->precision, nev, nacc, comp);
     if (!fn) return fail(ODE_ENOTSUP, "no kernel for this model/method");
     int nb = 0;
     hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0);
@@ -227,7 +248,7 @@ int ode_ensemble_query(const ode_ensemble *e, ode_ensemble_info *info) {
   auto *m = const_cast<ode_ensemble *>(e);
   int bpc = e->last_blocks_per_cu;
   if (bpc == 0) {
-    int rc = query_blocks(m, e->block, 0, 0, &bpc);
+    int rc = query_blocks(m, e->block, 0, 0, -1, &bpc);
     if (rc != ODE_OK) return rc;
   }
   info->block_size = e->block;
@@ -315,7 +336,7 @@ static int validate(const ode_ensemble *e, const ode_solve_args *a) {
 
 // Launch parameters of one solve (arguments already validated).
 static int prepare_launch(ode_ensemble *e, const ode_solve_args *a, Params &prm, int &nev,
-                          int &nacc, int &grid) {
+                          int &nacc, int &comp, int &grid) {
   std::memset(&prm, 0, sizeof prm);
   Control &c = prm.c;
   for (int i = 0; i < ODE_MAX_STATE; ++i) {
@@ -344,8 +365,9 @@ static int prepare_launch(ode_ensemble *e, const ode_solve_args *a, Params &prm,
 
   nev = event_slots(a->n_events);
   nacc = acc_slots(a->n_accessories);
+  comp = watched_component(a);
   int bpc = 0;
-  int rc = query_blocks(e, e->block, nev, nacc, &bpc);
+  int rc = query_blocks(e, e->block, nev, nacc, comp, &bpc);
   if (rc != ODE_OK) return rc;
   const int64_t max_grid = (int64_t)bpc * e->compute_units;
   const int64_t need = (a->n_systems + e->block - 1) / e->block;
@@ -379,10 +401,10 @@ int ode_ensemble_solve(ode_ensemble *e, const ode_solve_args *a, void *hip_strea
   if (rc != ODE_OK) return rc;
   if (a->n_systems == 0) return ODE_OK;
   Params prm;
-  int nev = 0, nacc = 0, grid = 0;
-  rc = prepare_launch(e, a, prm, nev, nacc, grid);
+  int nev = 0, nacc = 0, comp = -1, grid = 0;
+  rc = prepare_launch(e, a, prm, nev, nacc, comp, grid);
   if (rc != ODE_OK) return rc;
-  hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid,
+  hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, comp, prm, grid,
                                      e->block, static_cast<hipStream_t>(hip_stream));
   if (err != hipSuccess) return hip_fail(err, "integrator launch");
   return ODE_OK;
@@ -461,14 +483,14 @@ extern "C" int ode_ensemble_solve_noalloc(const ode_ensemble_desc *desc, const o
   if (rc != ODE_OK) return rc;
 
   Params prm;
-  int nev = 0, nacc = 0, grid = 0;
-  rc = prepare_launch(&e, a, prm, nev, nacc, grid);
+  int nev = 0, nacc = 0, comp = -1, grid = 0;
+  rc = prepare_launch(&e, a, prm, nev, nacc, comp, grid);
   if (rc != ODE_OK) return rc;
   const hipStream_t st = static_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(clear_scratch, dim3(1), dim3(64), 0, st, e.queue, kScratchWords);
   err = hipGetLastError();
   if (err != hipSuccess) return hip_fail(err, "clearing the scratch counters");
-  err = launch_integrator(e.model, e.method, e.precision, nev, nacc, prm, grid, e.block, st);
+  err = launch_integrator(e.model, e.method, e.precision, nev, nacc, comp, prm, grid, e.block, st);
   if (err != hipSuccess) return hip_fail(err, "integrator launch");
   return ODE_OK;
 }
@@ -602,8 +624,8 @@ extern "C" int ode_serve_launch(ode_serve *s, ode_ensemble *e, const ode_solve_a
   if (rc != ODE_OK) return rc;
   if (v.ld < 1) return fail(ODE_EINVAL, "ld must be >= 1");
   Params prm;
-  int nev = 0, nacc = 0, grid = 0;
-  rc = prepare_launch(e, &v, prm, nev, nacc, grid);
+  int nev = 0, nacc = 0, comp = -1, grid = 0;
+  rc = prepare_launch(e, &v, prm, nev, nacc, comp, grid);
   if (rc != ODE_OK) return rc;
   if (max_workgroups > 0 && grid > max_workgroups) grid = max_workgroups;
   Arrays &arr = prm.a;
@@ -617,7 +639,7 @@ extern "C" int ode_serve_launch(ode_serve *s, ode_ensemble *e, const ode_solve_a
   arr.n_req = s->max_requests;
   arr.idle_polls = idle_polls;
   e->last_grid = grid;
-  const hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid,
+  const hipError_t err = launch_integrator(e->model, e->method, e->precision, nev, nacc, comp, prm, grid,
                                            e->block, static_cast<hipStream_t>(hip_stream));
   if (err != hipSuccess) return hip_fail(err, "served launch");
   return ODE_OK;
@@ -628,8 +650,8 @@ static int record_segments(ode_ensemble *e, const ode_solve_args *a, int32_t n_s
                            double segment, int32_t first_snapshot, double *snapshots,
                            hipGraphExec_t *out) {
   Params prm;
-  int nev = 0, nacc = 0, grid = 0;
-  int rc = prepare_launch(e, a, prm, nev, nacc, grid);
+  int nev = 0, nacc = 0, comp = -1, grid = 0;
+  int rc = prepare_launch(e, a, prm, nev, nacc, comp, grid);
   if (rc != ODE_OK) return rc;
   const int rows = e->n_state + 2 * a->n_accessories;
   hipStream_t cs = e->capture_stream;
@@ -639,7 +661,7 @@ static int record_segments(ode_ensemble *e, const ode_solve_args *a, int32_t n_s
   for (int32_t k = 0; k < n_segments && first == hipSuccess; ++k) {
     first = launch_set_horizon(a->time_domain, a->ld, a->n_systems, a->system_index, segment, cs);
     if (first == hipSuccess)
-      first = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid, e->block,
+      first = launch_integrator(e->model, e->method, e->precision, nev, nacc, comp, prm, grid, e->block,
                                 cs);
     if (first == hipSuccess && k >= first_snapshot)
       first = launch_snapshot(a->state, e->n_state, a->accessories, 2 * a->n_accessories, a->ld,
@@ -768,12 +790,12 @@ int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *a, double probe_fra
       x = hipMemcpyAsync(c.next_h, a->next_h, sizeof(double) * ld, hipMemcpyDeviceToDevice, st);
     if (x != hipSuccess) return hip_fail(x, "preparing a probe");
     Params prm;
-    int nev = 0, nacc = 0, grid = 0;
-    int r = prepare_launch(e, &pa, prm, nev, nacc, grid);
+    int nev = 0, nacc = 0, comp = -1, grid = 0;
+    int r = prepare_launch(e, &pa, prm, nev, nacc, comp, grid);
     if (r != ODE_OK) return r;
     x = hipEventRecord(ev0, st);
     if (x == hipSuccess)
-      x = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid, block, st);
+      x = launch_integrator(e->model, e->method, e->precision, nev, nacc, comp, prm, grid, block, st);
     if (x == hipSuccess) x = hipEventRecord(ev1, st);
     if (x == hipSuccess) x = hipEventSynchronize(ev1);
     float f = 0.0f;
@@ -794,7 +816,8 @@ int ode_ensemble_tune(ode_ensemble *e, const ode_solve_args *a, double probe_fra
   for (int b : kBlocks) {
     int full = 0;
     e->cap = 0;
-    rc = query_blocks(e, b, event_slots(a->n_events), acc_slots(a->n_accessories), &full);
+    rc = query_blocks(e, b, event_slots(a->n_events), acc_slots(a->n_accessories),
+                      watched_component(a), &full);
     for (int half = 0; half < 2 && rc == ODE_OK; ++half) {
       const int cap = half ? full / 2 : 0;
       if (half && cap < 1) continue;
@@ -838,7 +861,8 @@ int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *a, double probe_fra
     return fail(ODE_EINVAL, "probe_tolerance_scale must be finite and >= 1");
   const int64_t n = a->n_systems, ld = a->ld;
   int bpc = 0;
-  rc = query_blocks(e, e->block, event_slots(a->n_events), acc_slots(a->n_accessories), &bpc);
+  rc = query_blocks(e, e->block, event_slots(a->n_events), acc_slots(a->n_accessories),
+                    watched_component(a), &bpc);
   if (rc != ODE_OK) return rc;
   const int64_t max_grid = (int64_t)bpc * e->compute_units;
   const int64_t need = (n + e->block - 1) / e->block;
@@ -888,10 +912,10 @@ int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *a, double probe_fra
     x = hipMemcpyAsync(c.next_h, a->next_h, sizeof(double) * ld, hipMemcpyDeviceToDevice, st);
   if (x != hipSuccess) return hip_fail(x, "preparing the probe");
   Params prm;
-  int nev = 0, nacc = 0, grid = 0;
-  rc = prepare_launch(e, &pa, prm, nev, nacc, grid);
+  int nev = 0, nacc = 0, comp = -1, grid = 0;
+  rc = prepare_launch(e, &pa, prm, nev, nacc, comp, grid);
   if (rc != ODE_OK) return rc;
-  x = launch_integrator(e->model, e->method, e->precision, nev, nacc, prm, grid, e->block, st);
+  x = launch_integrator(e->model, e->method, e->precision, nev, nacc, comp, prm, grid, e->block, st);
   if (x != hipSuccess) return hip_fail(x, "launching the probe");
 
   // per-position cost: the probe's attempts of the position's system

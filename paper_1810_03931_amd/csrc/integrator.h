@@ -95,12 +95,13 @@ struct Params {
 inline int event_slots(int n_events) { return n_events == 0 ? 0 : (n_events == 1 ? 1 : 4); }
 inline int acc_slots(int n_acc) { return n_acc == 0 ? 0 : (n_acc <= 2 ? 2 : 4); }
 
-// The kernel for (model, method, precision, event slots, accessory slots), or
-// nullptr.
-const void *integrator_kernel(int model, int method, int prec, int nev, int nacc);
+// The kernel for (model, method, precision, event slots, accessory slots,
+// watched component: 0 or 1 when every event and extremum accessory watches
+// that component, else -1), or nullptr.
+const void *integrator_kernel(int model, int method, int prec, int nev, int nacc, int comp);
 
 // Launch it with `grid` workgroups of `block` threads on `stream`.
-hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc,
+hipError_t launch_integrator(int model, int method, int prec, int nev, int nacc, int comp,
                              const Params &prm, int grid, int block, hipStream_t stream);
 
 // Repeated-horizon helpers (segments.hip): set t1 = t0 + segment for every

@@ -67,6 +67,18 @@ __device__ __forceinline__ double pick(const double (&y)[N], int c) {
   return __longlong_as_double((long long)r);
 }
 
+// y[c] for the component every event and accessory of the launch watches:
+// COMP >= 0 is that component known at compile time (a register read), -1 a
+// run-time component (pick).  The launch chooses COMP from its specs, so the
+// results are the same either way.
+template <int COMP, int N>
+__device__ __forceinline__ double cpick(const double (&y)[N], int c) {
+  if constexpr (COMP >= 0 && COMP < N)
+    return y[COMP];
+  else
+    return pick(y, c);
+}
+
 // y[c] <- v for a run-time component index c (bitmask blend, as in pick).
 template <int N>
 __device__ __forceinline__ void put(double (&y)[N], int c, double v) {
@@ -434,7 +446,7 @@ __device__ __forceinline__ HotControl<N, EV, AC> hot_control(const Control &c) {
   return h;
 }
 
-template <class M, int METHOD, int PREC, int NEV, int NACC>
+template <class M, int METHOD, int PREC, int NEV, int NACC, int COMP>
 __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
   const Control &c = prm.c;
   constexpr int N = M::NS;
@@ -495,7 +507,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
           accv[k] = 0.0;  // sum of ln y[c] at the sections
           acct[k] = 0.0;  // number of sections added
         } else {
-          accv[k] = pick(y, c.acc[k].component);
+          accv[k] = cpick<COMP>(y, c.acc[k].component);
           acct[k] = t;
         }
       }
@@ -691,7 +703,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             for (int j = 0; j < NEV; ++j) {
               zone[j] = cnt[j] = wcnt[j] = 0;
               if (j < c.n_events) {
-                F[j] = pick(y, c.ev[j].component) - c.ev[j].level;
+                F[j] = cpick<COMP>(y, c.ev[j].component) - c.ev[j].level;
                 // an initial point inside a zone is not an event (paper Sec. 7.2)
                 if (fabs(F[j]) <= c.ev[j].tolerance) leaving |= 1u << j;
               }
@@ -833,7 +845,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
         for (int j = 0; j < NEV; ++j) {
           if (j < hc.n_events && !((leaving >> j) & 1u)) {
-            const double Fn = pick(yn, hc.ev_comp[j]) - hc.ev_level[j];
+            const double Fn = cpick<COMP>(yn, hc.ev_comp[j]) - hc.ev_level[j];
             const int d = detect(F[j], Fn, hc.ev_dir[j], hc.ev_tol[j]);
             cross |= (d == 1 ? 1u : 0u) << j;
             land |= (d == 2 ? 1u : 0u) << j;
@@ -854,7 +866,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
               loc_tol = hc.ev_tol[j];
               ga = F[j];
             }
-          gb = pick(yn, loc_c) - loc_level;
+          gb = cpick<COMP>(yn, loc_c) - loc_level;
           loc_pos = ga > 0.0;
           lo = 0.0;
           hi = h_att;
@@ -880,7 +892,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
       }
     } else {
       // one secant iterate of the location of event J
-      const double gc = pick(yn, loc_c) - loc_level;
+      const double gc = cpick<COMP>(yn, loc_c) - loc_level;
       ++loc_it;
       const bool found = fabs(gc) <= loc_tol;
       if (found || loc_it >= kSecantMaxIter) {
@@ -894,7 +906,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
         for (int j = 0; j < NEV; ++j) {
           if (j < hc.n_events && (1u << j) != loc_bit && !((leaving >> j) & 1u)) {
-            const double Fn = pick(yn, hc.ev_comp[j]) - hc.ev_level[j];
+            const double Fn = cpick<COMP>(yn, hc.ev_comp[j]) - hc.ev_level[j];
             det |= (detect(F[j], Fn, hc.ev_dir[j], hc.ev_tol[j]) != 0 ? 1u : 0u) << j;
           }
         }
@@ -935,7 +947,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
         for (int k = 0; k < NACC; ++k)
           if (k < hc.n_acc && hc.acc_kind[k] != kAccLogReset) {
-            const double v = pick(y, hc.acc_comp[k]);
+            const double v = cpick<COMP>(y, hc.acc_comp[k]);
             const bool better = (hc.acc_kind[k] == kAccMax) ? (v > accv[k]) : (v < accv[k]);
             accv[k] = better ? v : accv[k];
             acct[k] = better ? t : acct[k];
@@ -990,7 +1002,7 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 #pragma unroll
       for (int j = 0; j < NEV; ++j) {
         if (j < hc.n_events) {
-          F[j] = pick(y, hc.ev_comp[j]) - hc.ev_level[j];
+          F[j] = cpick<COMP>(y, hc.ev_comp[j]) - hc.ev_level[j];
           const bool inside = fabs(F[j]) <= hc.ev_tol[j];
           const uint32_t bit = 1u << j;
           if (((det | ~leaving) & bit) != 0) {
@@ -1028,37 +1040,48 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
 }
 
 // Instantiation table for one model: kernels for both methods, both
-// precisions and every compiled (event slots, accessory slots) pair.
+// precisions and every compiled (event slots, accessory slots) pair, each with
+// run-time components; the FP64 kernels of the slot pairs the sweeps use most
+// (one event, two accessories, or both) also with components 0 and 1 fixed at
+// compile time.
 template <class M>
 struct ModelKernels {
-  template <int METHOD, int PREC, int NEV, int NACC>
+  template <int METHOD, int PREC, int NEV, int NACC, int COMP>
   static const void *fn() {
-    return reinterpret_cast<const void *>(&ode_integrate<M, METHOD, PREC, NEV, NACC>);
+    return reinterpret_cast<const void *>(&ode_integrate<M, METHOD, PREC, NEV, NACC, COMP>);
+  }
+  template <int METHOD, int PREC, int NEV, int NACC>
+  static const void *by_comp(int comp) {
+    if constexpr (PREC == kPrecFP64 && ((NEV == 1 && NACC <= 2) || (NEV == 0 && NACC == 2))) {
+      if (comp == 0) return fn<METHOD, PREC, NEV, NACC, 0>();
+      if (comp == 1) return fn<METHOD, PREC, NEV, NACC, 1>();
+    }
+    return fn<METHOD, PREC, NEV, NACC, -1>();
   }
   template <int METHOD, int PREC>
-  static const void *by_slots(int nev, int nacc) {
+  static const void *by_slots(int nev, int nacc, int comp) {
     switch (nev * 10 + nacc) {
-      case 0: return fn<METHOD, PREC, 0, 0>();
-      case 2: return fn<METHOD, PREC, 0, 2>();
-      case 4: return fn<METHOD, PREC, 0, 4>();
-      case 10: return fn<METHOD, PREC, 1, 0>();
-      case 12: return fn<METHOD, PREC, 1, 2>();
-      case 14: return fn<METHOD, PREC, 1, 4>();
-      case 40: return fn<METHOD, PREC, 4, 0>();
-      case 42: return fn<METHOD, PREC, 4, 2>();
-      case 44: return fn<METHOD, PREC, 4, 4>();
+      case 0: return by_comp<METHOD, PREC, 0, 0>(comp);
+      case 2: return by_comp<METHOD, PREC, 0, 2>(comp);
+      case 4: return by_comp<METHOD, PREC, 0, 4>(comp);
+      case 10: return by_comp<METHOD, PREC, 1, 0>(comp);
+      case 12: return by_comp<METHOD, PREC, 1, 2>(comp);
+      case 14: return by_comp<METHOD, PREC, 1, 4>(comp);
+      case 40: return by_comp<METHOD, PREC, 4, 0>(comp);
+      case 42: return by_comp<METHOD, PREC, 4, 2>(comp);
+      case 44: return by_comp<METHOD, PREC, 4, 4>(comp);
       default: return nullptr;
     }
   }
   template <int PREC>
-  static const void *by_method(int method, int nev, int nacc) {
-    if (method == kMethodRKCK45) return by_slots<kMethodRKCK45, PREC>(nev, nacc);
-    if (method == kMethodRK4) return by_slots<kMethodRK4, PREC>(nev, nacc);
+  static const void *by_method(int method, int nev, int nacc, int comp) {
+    if (method == kMethodRKCK45) return by_slots<kMethodRKCK45, PREC>(nev, nacc, comp);
+    if (method == kMethodRK4) return by_slots<kMethodRK4, PREC>(nev, nacc, comp);
     return nullptr;
   }
-  static const void *get(int method, int prec, int nev, int nacc) {
-    if (prec == kPrecFP64) return by_method<kPrecFP64>(method, nev, nacc);
-    if (prec == kPrecMixed) return by_method<kPrecMixed>(method, nev, nacc);
+  static const void *get(int method, int prec, int nev, int nacc, int comp) {
+    if (prec == kPrecFP64) return by_method<kPrecFP64>(method, nev, nacc, comp);
+    if (prec == kPrecMixed) return by_method<kPrecMixed>(method, nev, nacc, comp);
     return nullptr;
   }
 };

@@ -6,8 +6,8 @@
 
 namespace odeens {
 
-const void *kernels_duffing_lyapunov(int method, int prec, int nev, int nacc) {
-  return ModelKernels<DuffingLyapunov>::get(method, prec, nev, nacc);
+const void *kernels_duffing_lyapunov(int method, int prec, int nev, int nacc, int comp) {
+  return ModelKernels<DuffingLyapunov>::get(method, prec, nev, nacc, comp);
 }
 
 }  // namespace odeens

@@ -5,8 +5,8 @@
 
 namespace odeens {
 
-const void *kernels_relief_valve(int method, int prec, int nev, int nacc) {
-  return ModelKernels<ReliefValve>::get(method, prec, nev, nacc);
+const void *kernels_relief_valve(int method, int prec, int nev, int nacc, int comp) {
+  return ModelKernels<ReliefValve>::get(method, prec, nev, nacc, comp);
 }
 
 }  // namespace odeens
