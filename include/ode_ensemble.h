@@ -392,17 +392,29 @@ int ode_ensemble_plan(ode_ensemble *e, const ode_solve_args *args, double probe_
  * each is taken once.
  *
  * Every wait of the launch is bounded: a wave with no work polls the
- * published count, sleeping between polls, and leaves after idle_polls
- * empty polls in a row, or at once when the queue is closed and every
- * published position is taken.  A launch that has left while positions are
+ * published count, sleeping between polls.  It leaves at once when the queue
+ * is closed and every published position is taken; otherwise it keeps
+ * polling while some taken position is still being integrated (each within
+ * its step budget), and leaves after idle_polls empty polls in a row with
+ * every published position finished.  So a launch keeps all its waves while
+ * any of its work is in flight, and requests published meanwhile start on
+ * every idle lane, not only on those of the waves still integrating.  A launch that has left while positions are
  * still unpublished-or-untaken is simply launched again (ode_serve_launch
  * continues from the queue's position).  Results are bit-identical to an
  * ode_ensemble_solve of the same systems: no system's arithmetic depends on
  * its lane, its neighbours or the time it was admitted.
  *
+ * Streams: the queue owns a launch stream and a copy stream
+ * (ode_serve_stream), each created over every compute unit with a CU mask so
+ * that it has a hardware queue of its own.  Streams without one share the
+ * device's few hardware queues round-robin, and work on a stream that shares
+ * a hardware queue with a running persistent launch waits for that launch
+ * to end: an admission copy, a result copy or a relaunch of one served
+ * class would then wait for another class's launch.
+ *
  * Memory: the queue owns 32 bytes of device counters, max_requests int32
- * device counts, and max_requests int32 flags in coherent host memory.  One
- * served launch per queue may run at a time. */
+ * device counts, max_requests int32 flags in coherent host memory and its
+ * two streams.  One served launch per queue may run at a time. */
 typedef struct ode_serve ode_serve;
 
 /* Create a served queue on the current device for up to max_requests
@@ -412,6 +424,12 @@ int ode_serve_create(int32_t max_requests, ode_serve **out);
 /* Host pointer to the max_requests done flags (coherent host memory, written
  * by the GPU); NULL for a NULL queue. */
 volatile int32_t *ode_serve_done_flags(ode_serve *s);
+
+/* The queue's launch stream (which = 0) or copy stream (which = 1), as a
+ * hipStream_t owned by the queue; NULL for a NULL queue or another `which`.
+ * Any stream may be passed where the calls below take one; these two have
+ * hardware queues of their own (see above). */
+void *ode_serve_stream(ode_serve *s, int32_t which);
 
 /* Start a new session: published count, closed flag and queue position to
  * zero, every done flag to 0.  No launch may be running.  Synchronous on
@@ -443,7 +461,8 @@ int ode_serve_launch(ode_serve *s, ode_ensemble *e, const ode_solve_args *args,
                      const int32_t *request_of_slot, int32_t max_workgroups, int32_t idle_polls,
                      void *hip_stream);
 
-/* Release the queue's memory (no launch may be running).  NULL is ignored. */
+/* Release the queue's memory and streams (no launch may be running).  NULL
+ * is ignored. */
 void ode_serve_destroy(ode_serve *s);
 
 /* Launch facts for the handle.  Errors: ODE_EINVAL for NULL arguments. */

@@ -501,16 +501,21 @@ struct ode_serve {
   int device;
   int32_t max_requests;
   // device memory: [0] published positions (int64), [1] closed (int32 in the
-  // low half), then the queue counters [2][3] and the requests' counts
+  // low half), [2] next queue position, [3] finished positions
   int64_t *dev_words;
   int32_t *req_left;     // device [max_requests]
   int32_t *req_done;     // host, coherent and mapped [max_requests]
   int32_t *req_done_dev; // the same memory as the device addresses it
   int64_t *stage;        // host, pinned: staging words for the small copies
+  // the queue's own launch and copy streams, created with a mask of every
+  // compute unit: such streams get a hardware queue of their own instead of
+  // sharing one round-robin with the process's other streams, where a copy
+  // or a relaunch would wait behind another stream's persistent launch
+  hipStream_t streams[2];
 };
 
 namespace {
-constexpr int kServeWords = 4;   // published, closed, queue position, finished waves
+constexpr int kServeWords = 4;   // published, closed, queue position, finished positions
 constexpr int kStageCount = kServeWords + 1;   // + one staging word for a request's count
 
 int serve_copy_word(ode_serve *s, int index, int64_t value, hipStream_t st) {
@@ -546,6 +551,16 @@ extern "C" int ode_serve_create(int32_t max_requests, ode_serve **out) {
   if (err == hipSuccess)
     err = hipHostMalloc(reinterpret_cast<void **>(&s->stage), kStageCount * sizeof(int64_t),
                         hipHostMallocDefault);
+  int n_cu = 0;
+  if (err == hipSuccess)
+    err = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device);
+  if (err == hipSuccess) {
+    uint32_t mask[32] = {};
+    const int words = n_cu <= 0 ? 0 : (n_cu > 1024 ? 32 : (n_cu + 31) / 32);
+    for (int c = 0; c < words * 32 && c < n_cu; ++c) mask[c / 32] |= 1u << (c % 32);
+    for (int k = 0; k < 2 && err == hipSuccess; ++k)
+      err = hipExtStreamCreateWithCUMask(&s->streams[k], static_cast<uint32_t>(words), mask);
+  }
   if (err == hipSuccess) err = hipMemset(s->dev_words, 0, kServeWords * sizeof(int64_t));
   if (err == hipSuccess) err = hipMemset(s->req_left, 0, sizeof(int32_t) * max_requests);
   if (err == hipSuccess) err = hipDeviceSynchronize();
@@ -560,6 +575,8 @@ extern "C" int ode_serve_create(int32_t max_requests, ode_serve **out) {
 
 extern "C" void ode_serve_destroy(ode_serve *s) {
   if (!s) return;
+  for (hipStream_t st : s->streams)
+    if (st) (void)hipStreamDestroy(st);
   if (s->dev_words) (void)hipFree(s->dev_words);
   if (s->req_left) (void)hipFree(s->req_left);
   if (s->req_done) (void)hipHostFree(s->req_done);
@@ -569,6 +586,10 @@ extern "C" void ode_serve_destroy(ode_serve *s) {
 
 extern "C" volatile int32_t *ode_serve_done_flags(ode_serve *s) {
   return s ? s->req_done : nullptr;
+}
+
+extern "C" void *ode_serve_stream(ode_serve *s, int32_t which) {
+  return (s && (which == 0 || which == 1)) ? static_cast<void *>(s->streams[which]) : nullptr;
 }
 
 extern "C" int ode_serve_reset(ode_serve *s, void *copy_stream) {

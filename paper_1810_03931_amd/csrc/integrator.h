@@ -66,7 +66,9 @@ struct Arrays {
   const double *t_rec;  // per-system window start, or nullptr (Control::t_record)
   const double *tol;    // per-system [2*n_state][ld] rtol, atol, or nullptr
   int64_t n, ld;
-  unsigned long long *queue;  // [0] next queue position, [1] finished waves
+  // [0] next queue position, [1] finished waves (a served queue: finished
+  // positions, i.e. systems retired plus ring entries naming no slot)
+  unsigned long long *queue;
   uint32_t total_waves;
   // Served launches (avail != nullptr): queue position q holds the system in
   // slot index[q % ld]; positions below *avail are published (written by the

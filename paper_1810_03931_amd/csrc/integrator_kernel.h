@@ -541,12 +541,14 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
     }
     if (a.avail) {
       // served: the results are written back before the request's count
-      // drops, and the request's last system raises its flag in host memory
+      // drops, and the request's last system raises its flag in host memory;
+      // then the position counts as finished
       __threadfence_system();
       if (req >= 0 && req < a.n_req && atomicSub(a.req_left + req, 1) == 1) {
         __threadfence_system();
         __hip_atomic_store(a.req_done + req, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
+      atomicAdd(a.queue + 1, 1ull);
     }
     active = false;
   };
@@ -597,9 +599,13 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             idle = 0;
           } else if (all_idle) {
             // Nothing to take.  Leave once the host has closed the queue and
-            // every published position is taken, or after idle_polls empty
-            // polls in a row (a bounded wait: the host relaunches if work
-            // arrives later).
+            // every published position is taken; otherwise wait while some
+            // taken position is still being integrated (by other waves, each
+            // within its step budget, so the wait is bounded), and leave
+            // after idle_polls empty polls in a row with every published
+            // position finished.  The host relaunches when work arrives
+            // after that; a launch cannot be topped up while any of its
+            // waves runs, so its waves must not leave while work may follow.
             int stop = 0;
             if (lane == 0) {
               const int32_t cl = __hip_atomic_load(const_cast<int32_t *>(a.closed), __ATOMIC_ACQUIRE,
@@ -608,10 +614,13 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
                   const_cast<int64_t *>(a.avail), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
               const unsigned long long qv =
                   __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              stop = (cl != 0 && qv >= av) ? 1 : 0;
+              const unsigned long long fv =
+                  __hip_atomic_load(a.queue + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              stop = (cl != 0 && qv >= av) ? 1 : (fv < qv ? 2 : 0);
             }
             stop = __builtin_amdgcn_readfirstlane(stop);
-            if (stop != 0 || ++idle >= a.idle_polls) {
+            if (stop == 2) idle = 0;
+            if (stop == 1 || (stop == 0 && ++idle >= a.idle_polls)) {
               exhausted = true;
             } else {
               __builtin_amdgcn_s_sleep(127);
@@ -727,6 +736,8 @@ __global__ void __launch_bounds__(kMaxBlock) ode_integrate(const Params prm) {
             }
             if (status == kRunning && t >= t1) status = kDone;
             if (status != kRunning) retire();
+          } else if (served) {
+            atomicAdd(a.queue + 1, 1ull);  // a ring entry naming no slot: finished
           }
         }
       }

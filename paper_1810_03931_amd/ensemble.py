@@ -86,7 +86,7 @@ class Info(C.Structure):
 EXPORTS = ("ode_ensemble_model_dims", "ode_ensemble_create", "ode_ensemble_solve",
            "ode_ensemble_solve_noalloc", "ode_ensemble_solve_segments", "ode_ensemble_tune",
            "ode_ensemble_plan", "ode_plan_order", "ode_serve_create", "ode_serve_done_flags",
-           "ode_serve_reset", "ode_serve_begin_request", "ode_serve_publish", "ode_serve_close",
+           "ode_serve_stream", "ode_serve_reset", "ode_serve_begin_request", "ode_serve_publish", "ode_serve_close",
            "ode_serve_launch", "ode_serve_destroy", "ode_ensemble_query", "ode_ensemble_destroy",
            "ode_ensemble_last_error")
 
@@ -145,6 +145,8 @@ def load_library(path: str = LIB_PATH):
     L.ode_serve_create.restype = C.c_int
     L.ode_serve_done_flags.argtypes = [C.c_void_p]
     L.ode_serve_done_flags.restype = C.c_void_p
+    L.ode_serve_stream.argtypes = [C.c_void_p, C.c_int32]
+    L.ode_serve_stream.restype = C.c_void_p
     for f in ("ode_serve_reset", "ode_serve_close"):
         getattr(L, f).argtypes = [C.c_void_p, C.c_void_p]
         getattr(L, f).restype = C.c_int
@@ -453,6 +455,15 @@ class ServedQueue:
         self.done = np.ctypeslib.as_array(C.cast(flags, C.POINTER(C.c_int32)),
                                           shape=(self.max_requests,))
 
+    def streams(self, device=None):
+        """The queue's own (launch, copy) streams as torch external streams:
+        each has a hardware queue of its own, so neither waits behind another
+        stream's persistent launch."""
+        import torch
+        L = load_library()
+        return tuple(torch.cuda.ExternalStream(L.ode_serve_stream(self._h, k), device=device)
+                     for k in (0, 1))
+
     def close_queue(self, stream):
         _check(load_library().ode_serve_close(self._h, C.c_void_p(stream.cuda_stream)))
 
@@ -507,7 +518,32 @@ def _hip_runtime():
         _hip.hipMemcpy2DAsync.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
                                           C.c_size_t, C.c_size_t, C.c_int, C.c_void_p]
         _hip.hipMemcpy2DAsync.restype = C.c_int
+        _hip.hipExtStreamCreateWithCUMask.argtypes = [C.POINTER(C.c_void_p), C.c_uint32,
+                                                      C.POINTER(C.c_uint32)]
+        _hip.hipExtStreamCreateWithCUMask.restype = C.c_int
     return _hip
+
+
+def dedicated_stream(device=None):
+    """A new stream with a hardware queue of its own, as a torch external
+    stream: created over every compute unit with a CU mask
+    (hipExtStreamCreateWithCUMask).  Streams without one share the device's
+    few hardware queues round-robin, and work on a stream that shares a queue
+    with a running persistent launch waits for that launch to end.  The
+    stream lives until the process ends."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
+        else torch.device(device)
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    words = (n_cu + 31) // 32
+    mask = (C.c_uint32 * words)(*[(1 << min(32, n_cu - 32 * w)) - 1 for w in range(words)])
+    hip = _hip_runtime()
+    s = C.c_void_p()
+    with torch.cuda.device(dev):
+        rc = hip.hipExtStreamCreateWithCUMask(C.byref(s), C.c_uint32(words), mask)
+    if rc != 0:
+        raise OdeError(EHIP, f"hipExtStreamCreateWithCUMask failed ({rc})")
+    return torch.cuda.ExternalStream(s.value, device=dev)
 
 
 def copy_columns(dst, dst_col: int, src, src_col: int, ncols: int, stream) -> None:

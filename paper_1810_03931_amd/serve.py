@@ -89,7 +89,7 @@ def _tolerances(pb: I.Problem) -> np.ndarray:
 class _Slot:
     def __init__(self, torch, device, precision, block_size):
         self.torch = torch
-        self.stream = torch.cuda.Stream(device=device)
+        self.stream = E.dedicated_stream(device)   # never waits behind another slot's launch
         self.device = device
         self.precision = precision
         self.block_size = block_size
@@ -256,8 +256,9 @@ class _Resident:
         self.out = self.ens.outputs(C, n_accessories=len(opts.get("accessories", [])),
                                     n_events=len(opts["events"]), device=device)
         self.queue = E.ServedQueue(max_requests)
-        self.stream = torch.cuda.Stream(device=device)
-        self.copy = torch.cuda.Stream(device=device)
+        # the queue's own streams: a class's copies and relaunches never wait
+        # behind another class's running launch
+        self.stream, self.copy = self.queue.streams(device)
         self.max_requests = int(max_requests)
         self.max_workgroups = int(max_workgroups)
         self.idle_polls = int(idle_polls)
