@@ -164,18 +164,31 @@ typedef const double *PowTableRef;
 inline PowTableRef pow_table() { return kPowTable; }
 #endif
 
+// 2^n * v for an integral n; n outside the int range (where the result is
+// replaced anyway) is clamped first, so the conversion is always defined.
+__host__ __device__ __forceinline__ double scale_by_pow2(double v, double n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ldexp(v, static_cast<int>(n));   // the hardware conversion saturates
+#else
+  return ldexp(v, static_cast<int>(fmin(fmax(n, -4096.0), 4096.0)));
+#endif
+}
+
+// The main path runs for every operand and the special cases replace its
+// result at the end (selects, one branch for pow_special), so a wave pays no
+// branch and exec-mask bookkeeping for cases its lanes never reach.
 __host__ __device__ __forceinline__ double pow_pos(double x, double c) {
   constexpr double kInf = __builtin_huge_val();
   // a finite negative base is defined for integer exponents: |x|^c, negated
   // for odd c
   const bool neg_ok = x < 0.0 && x > -kInf && c == rint(c);
-  if (!((x > 0.0 && x < kInf) || neg_ok) || !(fabs(c) < kInf)) return pow_special(x, c);
+  const bool ordinary = ((x > 0.0 && x < kInf) || neg_ok) && fabs(c) < kInf;
   const bool negate = neg_ok && rint(0.5 * c) != 0.5 * c;   // an odd integer
-  x = fabs(x);
+  const double ax = ordinary ? fabs(x) : 1.0;
   const PowTableRef T = pow_table();
   const double kLn2Hi = T[kPowLn2Hi], kLn2Lo = T[kPowLn2Lo];
   int e = 0;
-  double m = frexp(x, &e);                            // m in [1/2, 1)
+  double m = frexp(ax, &e);                           // m in [1/2, 1)
   if (m < T[kPowSqrtHalf]) {                          // below 1/sqrt 2
     m = m + m;
     e -= 1;
@@ -204,8 +217,6 @@ __host__ __device__ __forceinline__ double pow_pos(double x, double c) {
   const double ll = lo - (lh - s);
   const double zh = c * lh;
   const double zl = fma(c, lh, -zh) + c * ll;
-  if (zh > T[kPowOver]) return negate ? -kInf : kInf;
-  if (zh < T[kPowUnder]) return negate ? -0.0 : 0.0;   // below the subnormals
   const double n = rint(zh * T[kPowInvLn2]);
   const double rh = fma(-n, kLn2Hi, zh);              // exact
   const double t = fma(-n, kLn2Lo, zl);
@@ -219,8 +230,12 @@ __host__ __device__ __forceinline__ double pow_pos(double x, double c) {
   const double q = fma(r4, fma(r4, qc, qb), qa);
   const double em1 = fma(r2, q, r);                   // exp(r) - 1
   const double v = 1.0 + fma(em1, rl, em1 + rl);      // exp(r + rl)
-  const double res = ldexp(v, static_cast<int>(n));
-  return negate ? -res : res;
+  double res = scale_by_pow2(v, n);
+  res = (zh > T[kPowOver]) ? kInf : res;              // overflow
+  res = (zh < T[kPowUnder]) ? 0.0 : res;              // below the subnormals
+  res = negate ? -res : res;
+  if (!ordinary) res = pow_special(x, c);
+  return res;
 }
 
 // sin and cos of (base + delta) from sb = sin(base), cb = cos(base), for
