@@ -174,6 +174,23 @@ __host__ __device__ __forceinline__ double scale_by_pow2(double v, double n) {
 #endif
 }
 
+// 1/d, correctly rounded, for 1 <= d < 4.  On the device: the hardware
+// reciprocal refined by two Newton steps and the quotient corrected by its
+// FMA residual -- the steps of the compiler's division sequence, without the
+// operand scaling and special-case fix-up that a divisor in this range never
+// needs, so the result is the same as that of 1.0 / d.
+__host__ __device__ __forceinline__ double recip_1_to_4(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double q = r;                      // 1.0 * r
+  return fma(fma(-d, q, 1.0), r, q);
+#else
+  return 1.0 / d;
+#endif
+}
+
 // The main path runs for every operand and the special cases replace its
 // result at the end (selects, one branch for pow_special), so a wave pays no
 // branch and exec-mask bookkeeping for cases its lanes never reach.
@@ -196,7 +213,7 @@ __host__ __device__ __forceinline__ double pow_pos(double x, double c) {
   const double f = m - 1.0;                           // exact
   const double dh = m + 1.0;
   const double dl = m - (dh - 1.0);                   // m + 1 = dh + dl exactly
-  const double rd = 1.0 / dh;
+  const double rd = recip_1_to_4(dh);
   const double uh = f * rd;
   const double ul = (fma(-uh, dh, f) - uh * dl) * rd;
   // P(w) = sum_k w^k / (2k + 3), k = 0..9, w = u^2, in three blocks of
