@@ -285,9 +285,9 @@ __device__ __forceinline__ void rk4_attempt(double t, const double (&y)[M::NS],
 // log2/exp2, ~1e-7 relative) is refined by two Newton steps on x^-5 = E,
 // x <- x + x (1 - E x^5) / 5, whose error goes 1e-7 -> 3e-14 -> rounding;
 // outside [1e-30, 1e30] (where the factor is clamped anyway) the library
-// routine is used.
+// routine replaces the result (a branch no lane normally takes, after the
+// Newton steps rather than around them).
 __device__ __forceinline__ double inv_fifth_root(double E) {
-  if (!(E >= 1e-30 && E <= 1e30)) return pow(E, -0.2);
   const float lf = __builtin_amdgcn_logf(static_cast<float>(E));
   double x = static_cast<double>(__builtin_amdgcn_exp2f(-0.2f * lf));
 #pragma unroll
@@ -296,6 +296,7 @@ __device__ __forceinline__ double inv_fifth_root(double E) {
     const double x5 = x2 * x2 * x;
     x = fma(x * 0.2, fma(-E, x5, 1.0), x);
   }
+  if (!(E >= 1e-30 && E <= 1e30)) x = pow(E, -0.2);
   return x;
 }
 

@@ -112,6 +112,9 @@ def test_resident_results_same_alone_and_in_mix(ode):
                 assert np.array_equal(a.outputs[k], c.outputs[k], equal_nan=True), (prec, a.rid, k)
         st = srv.stats()
         assert st["launches"] >= 3
+        # every class launches and copies on its queue's own streams
+        handles = [h for c in srv.classes.values() for h in (c.stream.cuda_stream, c.copy.cuda_stream)]
+        assert len(set(handles)) == len(handles) == 2 * len(srv.classes)
         lat = np.array([r.latency for r in mixed])
         print(f"[serve] resident {prec}: {len(reqs)} requests identical alone, under Poisson "
               f"arrivals and in a burst; {st}; latency p50 {np.median(lat) * 1e3:.1f} ms",
