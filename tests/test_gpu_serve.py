@@ -120,3 +120,25 @@ def test_resident_results_same_alone_and_in_mix(ode):
               f"arrivals and in a burst; {st}; latency p50 {np.median(lat) * 1e3:.1f} ms",
               flush=True)
         srv.shutdown()
+
+
+def test_work_published_beside_a_long_chain_starts_on_every_lane(ode):
+    """A served launch keeps all its waves while any of its work is in flight,
+    so a large request that arrives while one wave integrates a long
+    single-system request starts on every idle lane and finishes first.  (Were
+    the idle waves to leave, it would run on the 63 idle lanes of that one
+    wave: about 4e6 attempts per lane, several times the long request.)"""
+    from paper_1810_03931_amd.serve import ResidentServer
+    km = I.CONFIGS["keller_miksis"]()
+    # about 1.1e6 attempts in one serial chain, against at most 2e5 for any bulk system
+    long = I.Request(0, km.subset([141]).with_horizon(32.0, t_record=0.0), 32)
+    bulk_pb = km.subset(I.stratified_sample(km.n, 16384, seed=5)).with_horizon(8.0, t_record=0.0)
+    bulk = I.Request(1, bulk_pb, 8)
+    srv = ResidentServer(precision="fp64", capacity=1 << 15, max_workgroups=64)
+    try:
+        a, b = srv.run([long, bulk], np.array([0.0, 0.3]), stall_s=120)
+    finally:
+        srv.shutdown()
+    print(f"[serve] long chain done at {a.done:.2f} s; bulk request of {bulk_pb.n} systems "
+          f"(arrived at 0.3 s) done at {b.done:.2f} s", flush=True)
+    assert b.done < a.done
