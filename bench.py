@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=0.0,
                     help="override rtol = atol of the sweep (0: the sweep's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", dest="served", action="store_false",
+                    help="leave the served-mix record out of the default run")
     ap.add_argument("--no-sub-records", dest="sub_records", action="store_false",
                     help="time the headline workload only (by default the Keller-Miksis, "
                          "relief-valve and RK4 Duffing sweeps follow, in sub-records)")
@@ -228,6 +230,30 @@ def measured_traffic(workload):
 # Further single-GPU workloads timed in the default run, each in a sub-record of
 # the same JSON line: (name, timed steps, warmup steps).
 SUB_WORKLOADS = (("keller_miksis", 2, 1), ("relief_valve", 3, 1), ("duffing_rk4", 10, 2))
+
+# The served mix in the default run: the first requests of the seeded mix (three
+# models, 256-65536 systems, 64-2048 periods, tolerances 1e-7-1e-6), all
+# arriving at once, on the resident server, in FP64 and with FP32 stages.
+SERVED_REQUESTS = 40
+
+
+def served_record(args):
+    from paper_1810_03931_amd import inputs as I, serve as S
+    reqs = I.served_mix(SERVED_REQUESTS)
+    state = {"last": None}
+
+    def progress(done, total, admitted):
+        step = (done // 10, admitted // 10)
+        if step != state["last"] or done == total:
+            state["last"] = step
+            print(f"[bench] served mix: {admitted}/{total} admitted, {done}/{total} done",
+                  file=sys.stderr, flush=True)
+
+    runs = S.serve_mix(reqs, "resident", ("fp64", "mixed"), (), progress=progress)
+    return {"requests": len(reqs), "arrivals": "all at t = 0 (saturation)",
+            "models": list(I.SERVED_MODELS), "sizes": [256, 65536], "periods": [64, 2048],
+            "tolerance": [1e-7, 1e-6], "server": "resident (continuous admission)",
+            "runs": runs}
 
 
 def bench_workload(torch, E, name, args, steps, warmup):
@@ -462,6 +488,9 @@ def main():
                 "flops_per_attempt_source", "attempts_per_launch")}
             torch.cuda.empty_cache()
         line["workloads"] = subs
+        if args.served:
+            line["served_mix"] = served_record(args)
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
         line["cpu_baseline_1core"] = cpu_baseline(pb, args.cpu_seconds, threads=1)
