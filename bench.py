@@ -63,10 +63,10 @@ def parse():
                          "instead of the recorded graph")
     ap.add_argument("--plan", type=float, default=-1.0, metavar="FRACTION",
                     help="plan the queue order inside every timed step from a probe over this "
-                         "fraction of the horizon at 100x the tolerances (ode_ensemble_plan); "
-                         "-1: 0.04 when every system is resident and two or more waves share "
+                         "fraction of the horizon at S times the tolerances (ode_ensemble_plan); "
+                         "-1: 0.02 when every system is resident and two or more waves share "
                          "each SIMD, 0: never")
-    ap.add_argument("--plan-tol-scale", type=float, default=100.0, metavar="S",
+    ap.add_argument("--plan-tol-scale", type=float, default=1000.0, metavar="S",
                     help="the plan's probe runs at S times the tolerances")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=0.0,
@@ -338,7 +338,7 @@ def bench_workload(torch, E, name, args, steps, warmup):
         info0 = ens.info()
         waves_per_simd = pb.n / (64.0 * 4 * max(info0["compute_units"], 1))
         if pb.n <= info0["resident_systems"] and waves_per_simd >= 2:
-            plan_frac = 0.04
+            plan_frac = 0.02
     print(f"[bench] {name}: {warmup} warmup + {steps} timed steps", file=sys.stderr, flush=True)
     for _ in range(warmup):
         step()

@@ -361,8 +361,8 @@ class Ensemble(_Solver):
                                                 C.c_void_p(stream.cuda_stream), C.byref(r)))
         return {f: getattr(r, f) for f, _ in TuneResult._fields_ if f != "reserved"}
 
-    def plan(self, time_domain, state, params, *, probe_fraction: float = 0.04,
-             probe_tolerance_scale: float = 100.0, next_h=None, system_index=None, stream=None,
+    def plan(self, time_domain, state, params, *, probe_fraction: float = 0.02,
+             probe_tolerance_scale: float = 1000.0, next_h=None, system_index=None, stream=None,
              **options: Any):
         """Queue order for a solve of this problem on this handle: a probe on
         private copies over the first ``probe_fraction`` of each horizon, with
