@@ -321,7 +321,9 @@ __device__ __forceinline__ void sincos_near(double arg, double base, double sb, 
 
 // sin/cos of the stage phases arg[1..S-1] from those of arg[0] = base.  When
 // every stage lies within 1/16 of the base (one decision per attempt, so the
-// lanes of a wave normally agree) the short rotation serves all stages.
+// lanes of a wave normally agree) the short rotation serves all stages; it is
+// evaluated unconditionally and replaced in the rare other case, so the
+// common path carries no if/else around it.
 template <int S>
 __device__ __forceinline__ void stage_sincos(const double (&arg)[S], double sb, double cb,
                                              double (&s)[S], double (&c)[S]) {
@@ -334,10 +336,9 @@ __device__ __forceinline__ void stage_sincos(const double (&arg)[S], double sb, 
   }
   s[0] = sb;
   c[0] = cb;
-  if (dmax <= kShortRotate) {
 #pragma unroll
-    for (int k = 1; k < S; ++k) rotate_short(d[k], sb, cb, s[k], c[k]);
-  } else {
+  for (int k = 1; k < S; ++k) rotate_short(d[k], sb, cb, s[k], c[k]);
+  if (!(dmax <= kShortRotate)) {
 #pragma unroll
     for (int k = 1; k < S; ++k) sincos_near(arg[k], arg[0], sb, cb, s[k], c[k]);
   }
